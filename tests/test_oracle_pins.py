@@ -1,0 +1,392 @@
+"""Pins of the CPU oracle against facts it does not compute itself.
+
+Each test checks the oracle against a closed form, a value the paper
+prints, a special case that reduces to a textbook routine, a brute-force
+enumeration on tiny inputs, or an exact hand-derived shader case, so that a
+plausible mistake (dropped term, wrong index, wrong cut rule, transposed
+operand, a missing clamp) fails at least one of them.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import vro
+from paper_1805_08893_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ALL = range(8)
+REUSE = [vro.STATIC_BALLOT, vro.STATIC_SORT, vro.STATIC_HASH, vro.DYN_SORT, vro.DYN_HASH,
+         vro.DYN_PHASH, vro.DYN_BALLOT]
+SORTS = (vro.STATIC_SORT, vro.DYN_SORT)
+DYN = (vro.DYN_SORT, vro.DYN_HASH, vro.DYN_PHASH, vro.DYN_BALLOT)
+BALLOT = (vro.STATIC_BALLOT, vro.DYN_BALLOT)
+
+
+def _identity_shader(kind=W.SHADER_MVP):
+    sp = W.make_shader(kind, 0)
+    sp.mvp = np.eye(4, dtype=np.float32).ravel()
+    sp.model = np.eye(3, 4, dtype=np.float32).ravel()
+    sp.normal = np.eye(3, dtype=np.float32).ravel()
+    return sp
+
+
+def _vbuf(p, n=(0, 0, 1), uv=(0.25, 0.75)):
+    return np.array([[*p, *n, *uv]], dtype=np.float32)
+
+
+# ---------------------------------------------------------------- brute force
+def brute_units(idx, begin, end, cap, tmax):
+    """Units as maximal feasible prefixes, by enumeration with Python sets."""
+    units, cur = [], begin
+    while cur < end:
+        best = cur + 1
+        for e in range(cur + 1, end + 1):
+            if e - cur <= tmax and len(set(idx[3 * cur:3 * e].tolist())) <= cap:
+                best = e
+        units.append(cur)
+        cur = best
+    return units
+
+
+def brute_draw(idx, strategy, batch_tris, max_unique):
+    """Expected units / local ids / invocation counts written from the
+    definitions: static ranges, maximal dynamic prefixes, rounds of <= 64
+    distinct, ascending ranks (numpy.unique) or dict insertion order."""
+    T = len(idx) // 3
+    if strategy == vro.NAIVE:
+        batches = list(range(T))
+    elif strategy in DYN:
+        batches = brute_units(idx, 0, T, max_unique, batch_tris)
+    else:
+        batches = list(range(0, T, batch_tris))
+    batches.append(T)
+    units = []
+    for b in range(len(batches) - 1):
+        if strategy in BALLOT:
+            units += brute_units(idx, batches[b], batches[b + 1], 64, 1 << 30)
+        else:
+            units.append(batches[b])
+    units.append(T)
+    local, inv = np.zeros(3 * T, np.int64), []
+    for u in range(len(units) - 1):
+        seg = idx[3 * units[u]:3 * units[u + 1]]
+        if strategy == vro.NAIVE:
+            ids = np.arange(len(seg))
+        elif strategy in SORTS:
+            uq = np.unique(seg)
+            ids = np.searchsorted(uq, seg)
+        else:
+            order = {}
+            for v in seg.tolist():
+                order.setdefault(v, len(order))
+            ids = np.array([order[v] for v in seg.tolist()])
+        local[3 * units[u]:3 * units[u + 1]] = ids
+        inv.append(int(ids.max()) + 1 if len(ids) else 0)
+    return np.array(units), local, np.array(inv)
+
+
+def _check_against_brute(idx, V, strategy, bt, nu):
+    verts = np.tile(np.arange(V, dtype=np.float32)[:, None], (1, 8))
+    sp = _identity_shader()
+    rc, r = vro.process_draw(idx, verts, sp, strategy, bt, {"max_unique": nu},
+                             corners=False, verts=False, tris=False)
+    assert rc == vro.OK
+    units, local, inv = brute_draw(idx, strategy, bt, nu)
+    np.testing.assert_array_equal(r["unit_offsets"], units)
+    np.testing.assert_array_equal(r["unit_invocations"], inv)
+    np.testing.assert_array_equal(r["local_idx"], local)
+    assert int(r["counters"][0]) == int(inv.sum())
+
+
+def test_brute_force_exhaustive_two_triangles():
+    """Every index buffer of 2 triangles over 4 vertices, several caps."""
+    for combo in itertools.product(range(4), repeat=6):
+        idx = np.array(combo, dtype=np.uint32)
+        for strategy, bt, nu in ((vro.DYN_HASH, 2, 3), (vro.DYN_SORT, 2, 4), (vro.DYN_BALLOT, 1, 3),
+                                 (vro.STATIC_SORT, 1, 0), (vro.STATIC_HASH, 2, 0),
+                                 (vro.STATIC_BALLOT, 2, 0), (vro.NAIVE, 1, 0)):
+            _check_against_brute(idx, 4, strategy, bt, nu)
+
+
+def test_brute_force_random_small():
+    rng = np.random.default_rng(5)
+    for trial in range(300):
+        T = int(rng.integers(1, 40))
+        V = int(rng.integers(1, 24))
+        idx = rng.integers(0, V, 3 * T).astype(np.uint32)
+        strategy = int(rng.integers(0, 8))
+        if strategy in DYN:
+            bt = int(rng.integers(1, 20))
+            nu = int(rng.integers(3, 12))
+        else:
+            bt = int(rng.integers(1, 30))
+            nu = 0
+        _check_against_brute(idx, V, strategy, bt, nu)
+
+
+def test_brute_force_ballot_rounds_overflow():
+    """Ballot rounds on all-distinct and mixed streams where 64 binds."""
+    rng = np.random.default_rng(9)
+    for V in (64, 100, 1000):
+        idx = rng.integers(0, V, 3 * 200).astype(np.uint32)
+        for bt in (21, 22, 64, 200):
+            _check_against_brute(idx, V, vro.STATIC_BALLOT, bt, 0)
+    idx = np.arange(3 * 100, dtype=np.uint32)
+    _check_against_brute(idx, 300, vro.STATIC_BALLOT, 100, 0)
+
+
+# ---------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("n", [2, 3, 64])
+def test_grid_closed_form(n):
+    m = W.grid_mesh(n, n, 1, "scan")
+    assert m.num_tris == 2 * (n - 1) ** 2
+    assert vro.count_unique(m.indices, m.num_verts) == n * n
+
+
+@pytest.mark.parametrize("k", [0, 1, 3, 5])
+def test_icosphere_closed_form(k):
+    m = W.icosphere_mesh(k, 2, "hilbert")
+    assert m.num_tris == 20 * 4 ** k
+    assert vro.count_unique(m.indices, m.num_verts) == 10 * 4 ** k + 2
+
+
+def _table1_ideal():
+    rows = []
+    with open(os.path.join(GOLDEN, "table1_closed_mesh_ideal_reuse.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append(float(line.split()[-1]))
+    return rows
+
+
+def test_ideal_reuse_matches_table1_closed_meshes():
+    """Ideal reuse of a closed sphere-like mesh rounds to Table 1's .833,
+    and each vertex is referenced about six times (Figure 1 caption)."""
+    m = W.icosphere_mesh(5, 2, "scan")
+    U = vro.count_unique(m.indices, m.num_verts)
+    ideal = 1.0 - U / len(m.indices)
+    assert round(ideal, 3) in _table1_ideal()
+    assert abs(len(m.indices) / U - 6.0) < 0.01
+    # the whole-mesh unit reaches it: static sort with N_p >= T shades U times
+    rc, r = vro.process_draw(m.indices[:3 * 256], m.vertices, _identity_shader(), vro.STATIC_SORT, 256,
+                             corners=False, verts=False)
+    assert int(r["counters"][0]) == vro.count_unique(m.indices[:3 * 256], m.num_verts)
+
+
+# ---------------------------------------------------------------- special cases
+def test_s1_naive_three_per_triangle():
+    m = W.grid_mesh(9, 7, 3, "random")
+    rc, r = vro.process_draw(m.indices, m.vertices, _identity_shader(), vro.NAIVE, 1)
+    assert rc == vro.OK and int(r["counters"][0]) == 3 * m.num_tris
+    np.testing.assert_array_equal(r["local_idx"], np.tile([0, 1, 2], m.num_tris))
+
+
+def test_s2_one_static_batch_is_global_sorted_unique():
+    m = W.grid_mesh(10, 10, 3, "hilbert")
+    sp = W.shader_for_mesh(m, W.SHADER_PHONG, 3, num_lights=4)
+    rc, r = vro.process_draw(m.indices, m.vertices, sp, vro.STATIC_SORT, 256)
+    uq = np.unique(m.indices)
+    assert int(r["counters"][0]) == len(uq)
+    np.testing.assert_array_equal(r["local_idx"], np.searchsorted(uq, m.indices))
+    np.testing.assert_array_equal(r["verts"], vro.shade(sp, m.vertices[uq]))
+
+
+def test_s3_dynamic_with_large_budget_equals_static():
+    m = W.icosphere_mesh(3, 4, "hilbert")
+    for st_dyn, st_static in ((vro.DYN_HASH, vro.STATIC_HASH), (vro.DYN_SORT, vro.STATIC_SORT)):
+        _, a = vro.process_draw(m.indices, m.vertices, _identity_shader(), st_dyn, 64,
+                                {"max_unique": 192}, corners=False, verts=False)
+        _, b = vro.process_draw(m.indices, m.vertices, _identity_shader(), st_static, 64,
+                                corners=False, verts=False)
+        for key in ("unit_offsets", "unit_invocations", "local_idx", "tris"):
+            np.testing.assert_array_equal(a[key], b[key])
+
+
+def test_s4_ballot_with_small_batches_equals_hash():
+    m = W.icosphere_mesh(3, 4, "random")
+    _, a = vro.process_draw(m.indices, m.vertices, _identity_shader(), vro.STATIC_BALLOT, 21,
+                            corners=False, verts=False)
+    _, b = vro.process_draw(m.indices, m.vertices, _identity_shader(), vro.STATIC_HASH, 21,
+                            corners=False, verts=False)
+    for key in ("unit_offsets", "unit_invocations", "local_idx", "tris"):
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+def test_s5_min_budget_all_distinct():
+    T = 50
+    idx = np.arange(3 * T, dtype=np.uint32)
+    verts = np.zeros((3 * T, 8), np.float32)
+    rc, r = vro.process_draw(idx, verts, _identity_shader(), vro.DYN_HASH, 10, {"max_unique": 3},
+                             corners=False, verts=False)
+    assert int(r["counters"][0]) == 3 * T and int(r["counters"][1]) == T
+
+
+def test_s7_all_equal_indices():
+    idx = np.zeros(3 * 100, dtype=np.uint32)
+    verts = np.zeros((1, 8), np.float32)
+    for st, bt, nunits in ((vro.STATIC_SORT, 7, 15), (vro.STATIC_BALLOT, 7, 15), (vro.DYN_HASH, 33, 4),
+                           (vro.DYN_BALLOT, 512, 1)):
+        rc, r = vro.process_draw(idx, verts, _identity_shader(), st, bt, corners=False, verts=False)
+        assert int(r["counters"][1]) == nunits and int(r["counters"][0]) == nunits
+
+
+def test_empty_draw():
+    rc, r = vro.process_draw(np.zeros(0, np.uint32), np.zeros((4, 8), np.float32), _identity_shader(),
+                             vro.DYN_HASH, 64)
+    assert rc == vro.OK and r["counters"].tolist() == [0, 0, 0, 0]
+
+
+def test_index_out_of_range_is_reported():
+    idx = np.array([0, 1, 4], dtype=np.uint32)
+    rc, r = vro.process_draw(idx, np.zeros((4, 8), np.float32), _identity_shader(), vro.STATIC_SORT, 4)
+    assert rc == vro.ERR_INDEX_RANGE and int(r["counters"][3]) == vro.ERR_INDEX_RANGE
+
+
+def test_argument_errors():
+    idx = np.zeros(6, np.uint32)
+    v = np.zeros((1, 8), np.float32)
+    sp = _identity_shader()
+    assert vro.process_draw(idx[:5], v, sp, vro.NAIVE, 1)[0] == vro.ERR_ARG          # not triangles
+    assert vro.process_draw(idx, v, sp, 8, 1)[0] == vro.ERR_ARG                      # strategy
+    assert vro.process_draw(idx, v, sp, vro.STATIC_SORT, 0)[0] == vro.ERR_ARG        # batch 0
+    assert vro.process_draw(idx, v, sp, vro.STATIC_SORT, 257)[0] == vro.ERR_ARG      # batch cap
+    assert vro.process_draw(idx, v, sp, vro.DYN_HASH, 64, {"max_unique": 2})[0] == vro.ERR_ARG
+    assert vro.process_draw(idx, v, sp, vro.DYN_HASH, 64, {"max_unique": 513})[0] == vro.ERR_ARG
+    assert vro.process_draw(idx, v, sp, vro.DYN_HASH, 64, {"hash_slots": 100})[0] == vro.ERR_ARG
+    sp.num_lights = 17
+    assert vro.process_draw(idx, v, sp, vro.NAIVE, 1)[0] == vro.ERR_ARG
+
+
+def test_dynamic_units_satisfy_caps_and_are_maximal():
+    m = W.icosphere_mesh(4, 6, "hilbert", swap_frac=0.05)
+    for nu, tmax in ((64, 85), (256, 341), (128, 128), (7, 1000)):
+        offs = vro.plan_dynamic(m.indices, m.num_verts, nu, tmax)
+        for b in range(len(offs) - 1):
+            t0, t1 = int(offs[b]), int(offs[b + 1])
+            assert 0 < t1 - t0 <= tmax
+            assert len(set(m.indices[3 * t0:3 * t1].tolist())) <= nu
+            if t1 < m.num_tris and t1 - t0 < tmax:
+                assert len(set(m.indices[3 * t0:3 * t1 + 3].tolist())) > nu
+
+
+# ---------------------------------------------------------------- FIFO cache
+def test_fifo_hand_examples():
+    strip = np.array([0, 1, 2, 1, 2, 3, 2, 3, 4], np.uint32)
+    assert vro.fifo_misses(strip, 5, 3) == 5
+    # FIFO (unlike LRU) does not refresh on a hit: 0 1 0 2 0 3 with k=2
+    seq = np.array([0, 1, 0, 2, 0, 3], np.uint32)
+    assert vro.fifo_misses(seq, 4, 2) == 5
+    m = W.icosphere_mesh(3, 1, "random")
+    U = vro.count_unique(m.indices, m.num_verts)
+    assert vro.fifo_misses(m.indices, m.num_verts, U) == U
+    assert vro.fifo_misses(m.indices, m.num_verts, 0) == len(m.indices)
+
+
+# ---------------------------------------------------------------- shading
+def test_mvp_identity_and_affine_exact():
+    sp = _identity_shader()
+    out = vro.shade(sp, _vbuf((0.5, -1.25, 3.0), (0, 0, 1)))[0]
+    np.testing.assert_array_equal(out[:9], [0.5, -1.25, 3.0, 1.0, 0, 0, 1, 0.25, 0.75])
+    np.testing.assert_array_equal(out[9:], sp.ambient)
+    # scale-and-translate rows: x' = 2x + 3, y' = y/2 - 1, z' = z, w = z (row 3 = (0,0,1,0))
+    sp.mvp = np.array([2, 0, 0, 3, 0, 0.5, 0, -1, 0, 0, 1, 0, 0, 0, 1, 0], np.float32)
+    out = vro.shade(sp, _vbuf((0.5, -1.25, 3.0)))[0]
+    np.testing.assert_array_equal(out[:4], [4.0, -1.625, 3.0, 3.0])
+    # normal matrix rows are applied as dot products with the input normal
+    sp.normal = np.array([0, 1, 0, 0, 0, 1, 1, 0, 0], np.float32)     # cyclic permutation
+    out = vro.shade(sp, _vbuf((0, 0, 0), (0.0, 3.0, 4.0)))[0]
+    np.testing.assert_array_equal(out[4:7], np.float32([0.6, 0.8, 0.0]))
+
+
+def test_phong_light_along_normal_exact():
+    sp = _identity_shader(W.SHADER_PHONG)
+    sp.num_lights, sp.kd, sp.ks, sp.katt = 1, 0.75, 0.25, 0.25
+    sp.ambient = np.float32([0.25, 0.125, 0.0])
+    sp.eye = np.float32([0, 0, 5])
+    lights = np.zeros((16, 6), np.float32)
+    lights[0] = [0, 0, 2, 1.0, 0.5, 2.0]        # d2 = 4 -> att = 1/(1+0.25*4) = 0.5
+    sp.lights = lights
+    out = vro.shade(sp, _vbuf((0, 0, 0)))[0]
+    # diffuse 1, reflection = n, view = n -> specular 1; k = 0.5*(0.25+0.75)
+    np.testing.assert_array_equal(out[9:], np.float32([0.25 + 0.5, 0.125 + 0.25, 1.0]))
+    # light behind the surface: both clamps give zero, colour = ambient
+    lights[0, 2] = -2.0
+    sp.lights = lights
+    out = vro.shade(sp, _vbuf((0, 0, 0)))[0]
+    np.testing.assert_array_equal(out[9:], sp.ambient)
+    # specular only, reflection at 90 degrees from the view: light along +x,
+    # normal +z -> ndl = 0 -> diffuse 0, r = -l -> dot(r, v) = 0
+    lights[0] = [2, 0, 0, 1, 1, 1]
+    sp.lights = lights
+    out = vro.shade(sp, _vbuf((0, 0, 0)))[0]
+    np.testing.assert_array_equal(out[9:], sp.ambient)
+
+
+def test_phong_specular_exponent():
+    """Mirror geometry with cos = 1/2 between reflection and view: the
+    specular term is (1/2)^(2^s) exactly."""
+    sp = _identity_shader(W.SHADER_PHONG)
+    sp.num_lights, sp.kd, sp.ks, sp.katt = 1, 0.0, 1.0, 0.0
+    sp.ambient = np.float32([0, 0, 0])
+    lights = np.zeros((16, 6), np.float32)
+    lights[0] = [0, 0, 1, 1, 1, 1]              # light along the normal: r = n
+    sp.lights = lights
+    # view direction (sqrt(3)/2, 0, 1/2) is not exact in float32; instead put
+    # the eye at (x, 0, 1) with |(x,0,1)| = 2 -> x = sqrt(3): check vs float64
+    for s in (0, 1, 3, 5):
+        sp.spec_squarings = s
+        sp.eye = np.float32([math.sqrt(3.0), 0.0, 1.0])
+        o32 = vro.shade(sp, _vbuf((0, 0, 0)))[0]
+        expect = 0.5 ** (2 ** s)
+        assert abs(o32[9] - expect) <= 1e-6 * max(expect, 1e-30) * (2 ** s) + 1e-12
+
+
+def test_offset_reaches_fixed_point():
+    """64 relaxation steps converge to the real root of
+    c3 h^3 + c2 h^2 + (c1 - 1) h + dot(cvec, p) = 0 (contraction ~0.75)."""
+    sp = _identity_shader(W.SHADER_OFFSET)
+    sp.iterations = 64
+    c = sp.coef.astype(np.float64)
+    for p in ((0.3, -0.2, 0.9), (1.0, 1.0, 1.0), (-2.0, 0.5, 0.1)):
+        out = vro.shade(sp, _vbuf(p, (0, 0, 1)))[0]
+        ph = float(np.dot(c[4:7], p))
+        roots = np.roots([c[3], c[2], c[1] - 1.0, ph])
+        real = roots[np.abs(roots.imag) < 1e-12].real
+        h = real[np.argmin(np.abs(real))]
+        assert abs(out[0] - np.float32(p[0])) == 0 and abs(out[1] - np.float32(p[1])) == 0
+        assert abs(float(out[2]) - (p[2] + h)) < 4e-6
+    sp.iterations = 0                            # no refinement: p unchanged
+    out = vro.shade(sp, _vbuf((0.3, -0.2, 0.9)))[0]
+    np.testing.assert_array_equal(out[:3], np.float32([0.3, -0.2, 0.9]))
+
+
+@pytest.mark.parametrize("kind,lights", [(W.SHADER_MVP, 0), (W.SHADER_PHONG, 8), (W.SHADER_PHONG, 16),
+                                         (W.SHADER_OFFSET, 0)])
+def test_fp32_program_within_rounding_of_fp64(kind, lights):
+    """The FP32 program stays within a derived bound of the same program in
+    float64: a few units in the last place per output, scaled by the
+    magnitudes involved (x32 for the specular power)."""
+    m = W.icosphere_mesh(3, 8, "scan")
+    sp = W.shader_for_mesh(m, kind, 8, num_lights=lights)
+    o32 = vro.shade(sp, m.vertices).astype(np.float64)
+    o64 = vro.shade(sp, m.vertices, f64=True)
+    scale = np.maximum(1.0, np.abs(o64))
+    rel = np.abs(o32 - o64) / scale
+    assert rel.max() < 64 * 2.0 ** -23, rel.max()
+
+
+def test_corners_equal_naive_shading_all_strategies():
+    """Invariant: whatever the strategy, corner k is the shaded vertex
+    idx[k] (bitwise), and all strategies emit identical corners."""
+    m = W.icosphere_mesh(3, 3, "hilbert", swap_frac=0.05)
+    sp = W.shader_for_mesh(m, W.SHADER_PHONG, 3, num_lights=4)
+    ref = vro.shade(sp, m.vertices[m.indices])
+    for st in ALL:
+        rc, r = vro.process_draw(m.indices, m.vertices, sp, st, 64)
+        np.testing.assert_array_equal(r["corners"], ref)
+        np.testing.assert_array_equal(r["verts"][r["tris"]], ref)
+        inv, U = int(r["counters"][0]), int(r["counters"][2])
+        assert U <= inv <= len(m.indices)
