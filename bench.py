@@ -1,0 +1,174 @@
+"""Benchmark of the geometry stage on one MI355X.
+
+Workload: icosphere subdivided 8 times (655,362 vertices, 1,310,720
+triangles), Hilbert order with 5% local swaps in windows of 256, FP32
+attributes, Phong shading with 8 point lights.  One step runs the whole hot
+path once over this draw for every strategy, each producing the per-corner
+shaded output and the invocation count:
+    dynamic batch plan (N_u = 256, N_pmax = 256), shared by the dynamic
+    strategies; naive; static wave64 ballot (64 triangles); dynamic sort,
+    hash and parallel hash (256 / 256).
+value = triangles processed per second over the whole step (all strategies,
+inputs resident in HBM).  Per-strategy throughput and shading rate are
+reported beside it, with the roofline of the dominant kernel and the CPU
+oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+METRIC = "triangles/s & shading rate per strategy vs no-reuse; p50/p99 draw latency"
+
+
+def shader_flops(sp):
+    """FP32 operations of one vertex-program evaluation (fma = 2, sqrt and
+    divide = 1 each), counted from the written program."""
+    mvp = 4 * 6 + 3 * 5 + 10
+    if sp.kind == 1:
+        return mvp + 18 + 13 + 48 * sp.num_lights
+    if sp.kind == 2:
+        return mvp + 11 + 9 * sp.iterations
+    return mvp
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-passes", type=int, default=1)
+    ap.add_argument("--level", type=int, default=8, help="icosphere subdivision level")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the geometry stage has no cross-GPU path "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1805_08893_amd import vr
+    from paper_1805_08893_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    mesh, sp = W.icosphere8_hilbert_phong8(level=args.level)
+    T, V = mesh.num_tris, mesh.num_verts
+    U = int(len(np.unique(mesh.indices)))
+    idx = torch.from_numpy(mesh.indices.view(np.int32)).cuda()
+    vtx = torch.from_numpy(mesh.vertices).cuda()
+    stage = vr.GeometryStage(0)
+    plan = torch.empty(T + 2, dtype=torch.int32, device="cuda")
+    NU, NP = 256, 256
+    strategies = [("naive", vr.VR_NAIVE, 1, {}),
+                  ("static_ballot", vr.VR_STATIC_BALLOT, 64, {}),
+                  ("dyn_sort", vr.VR_DYN_SORT, NP, dict(max_unique=NU, plan=plan)),
+                  ("dyn_hash", vr.VR_DYN_HASH, NP, dict(max_unique=NU, plan=plan)),
+                  ("dyn_phash", vr.VR_DYN_PHASH, NP, dict(max_unique=NU, plan=plan))]
+    res = {name: stage.alloc_outputs(T, s, bt, corners=True) for name, s, bt, _ in strategies}
+    opts = {name: vr.make_opts(**o) for name, _, _, o in strategies}
+    shader = vr.make_shader(sp)
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        if events is not None:
+            events["plan"][0].record(stream)
+        st = vr.vr_plan_dynamic(stage.ctx, idx, V, NU, NP, plan)
+        stage.check(st)
+        if events is not None:
+            events["plan"][1].record(stream)
+        for name, s, bt, _ in strategies:
+            if events is not None:
+                events[name][0].record(stream)
+            stage.check(vr.vr_process_draw(stage.ctx, idx, vtx, shader, s, bt, opts[name],
+                                           stage.describe(res[name])))
+            if events is not None:
+                events[name][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    st, _ = stage.sync()
+    stage.check(st)
+
+    names = ["plan"] + [s[0] for s in strategies]
+    ev = [{n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for n in names}
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(ev[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st, inv_total = stage.sync()
+    stage.check(st)
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    tris_step = T * len(strategies)
+    value = tris_step / (ms_step * 1e-3)
+    per = {}
+    for n in names:
+        ms = [ev[k][n][0].elapsed_time(ev[k][n][1]) for k in range(args.steps)]
+        per[n] = {"ms_mean": float(np.mean(ms)), "ms_p50": float(np.percentile(ms, 50)),
+                  "ms_p99": float(np.percentile(ms, 99))}
+    for name, s, bt, _ in strategies:
+        inv = int(res[name]["counters"][0].item())
+        p = per[name]
+        p.update({"tri_per_s": T / (p["ms_mean"] * 1e-3), "invocations": inv, "shading_rate": inv / U,
+                  "reuse": 1.0 - inv / (3.0 * T), "speedup_vs_naive": None})
+    for name, *_ in strategies:
+        per[name]["speedup_vs_naive"] = per["naive"]["ms_mean"] / per[name]["ms_mean"]
+
+    # dominant kernel: the slowest draw of the step
+    dom = max((s[0] for s in strategies), key=lambda n: per[n]["ms_mean"])
+    dom_ms = per[dom]["ms_mean"]
+    alg_bytes = 12 * T + 32 * U + 144 * T            # indices + each referenced vertex once + corners
+    alg_flops = per[dom]["invocations"] * shader_flops(sp)
+    gbs = alg_bytes / (dom_ms * 1e-3) / 1e9
+    tfl = alg_flops / (dom_ms * 1e-3) / 1e12
+    if gbs / HBM_PEAK_GBS >= tfl / FP32_VECTOR_PEAK_TFLOPS:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    else:
+        roof = {"bound": "alu", "achieved": tfl, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tfl / FP32_VECTOR_PEAK_TFLOPS}
+    roof.update({"traffic": None, "kernel": dom, "bytes_per_launch": alg_bytes, "flops_per_launch": alg_flops,
+                 "ms_per_launch": dom_ms, "hbm_frac": gbs / HBM_PEAK_GBS,
+                 "alu_frac": tfl / FP32_VECTOR_PEAK_TFLOPS})
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import vro
+        t_cpu, tris_cpu = 0.0, 0
+        for _ in range(args.cpu_passes):
+            for name, s, bt, o in strategies:
+                c0 = time.perf_counter()
+                rc, _ = vro.process_draw(mesh.indices, mesh.vertices, sp, s, bt,
+                                         {"max_unique": o.get("max_unique", 0)}, tris=False, verts=False,
+                                         local_idx=False, units=False)
+                t_cpu += time.perf_counter() - c0
+                tris_cpu += T
+        cpu = {"value": tris_cpu / t_cpu, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+               "sample": f"{args.cpu_passes} pass(es) of the full step (5 strategies x {T} triangles), "
+                         f"single-threaded C oracle, {t_cpu:.1f} s"}
+
+    line = {"metric": METRIC, "value": value, "unit": "triangles/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"icosphere{args.level}_hilbert_swap5_phong8", "triangles": T, "vertices": V,
+                       "unique_vertices": U, "strategies": [s[0] for s in strategies],
+                       "static_batch_tris": 64, "dynamic_max_unique": NU, "dynamic_max_tris": NP,
+                       "output": "per-corner shaded vertices + invocation counters"},
+            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per}
+    print(json.dumps(line), flush=True)
+    stage.close()
+
+
+if __name__ == "__main__":
+    main()

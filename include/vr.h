@@ -1,0 +1,206 @@
+/*
+ * vr.h -- C ABI of the MI355X geometry stage with on-the-fly vertex reuse
+ * (Kenzel, Kerbl, Tatzgern, Ivanchenko, Schmalstieg, Steinberger, "On-the-fly
+ * Vertex Reuse for Massively-Parallel Software Geometry Processing").
+ *
+ * Problem statement (Section 4.2, "Rasterization"): the geometry stage gets
+ * a stream of indices and a vertex buffer, groups the triangles into batches,
+ * shades each vertex a batch references once, and writes every triangle with
+ * its shaded vertices to an output queue.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are device pointers (HBM), caller-owned, and must
+ *    stay valid until the work enqueued on the context's stream completes.
+ *    Host structs (shader parameters, options, output descriptors) are copied
+ *    during the call.
+ *  - Work is enqueued on the context's HIP stream and the call returns
+ *    without waiting.  vr_sync() waits and reports device-side errors.
+ *  - Errors are returned as vr_status; nothing aborts or throws across the
+ *    ABI.  Argument errors are detected on the host before anything is
+ *    enqueued and leave every output untouched.  vr_last_error() returns a
+ *    text for the last failing call on a context.
+ *  - A context is used by one host thread at a time.
+ *
+ * Data layout (all little-endian, tightly packed):
+ *  - indices:  uint32[3T], a triangle list; triangle t uses entries 3t..3t+2
+ *              (Section 3).  Every index must be < num_vertices.
+ *  - vertices: float32[V][8] = {px, py, pz, nx, ny, nz, u, v}; 32-byte rows,
+ *              the buffer 16-byte aligned.
+ *  - a shaded vertex: float32[12] = {clip x, y, z, w, n'x, n'y, n'z, u, v,
+ *              r, g, b}, 48 bytes.
+ */
+#ifndef VR_H
+#define VR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vr_ctx vr_ctx;
+
+typedef enum {
+    VR_OK = 0,
+    VR_ERR_ARG = 1,          /* invalid argument; nothing was enqueued          */
+    VR_ERR_INDEX_RANGE = 2,  /* (from vr_sync) an index >= num_vertices; the
+                                outputs of the affected draws are undefined    */
+    VR_ERR_CAPACITY = 3,     /* an output capacity is below the documented bound */
+    VR_ERR_OOM = 4,          /* device memory for the context's scratch failed  */
+    VR_ERR_DEVICE = 5,       /* a HIP call failed, or a device-side wait ran out */
+    VR_ERR_BUSY = 6          /* reserved                                         */
+} vr_status;
+
+/*
+ * Reuse strategies (Section 3).  A "unit" is the set of triangles that share
+ * one deduplication: a static batch, a dynamic batch, or a ballot round.
+ *  NAIVE          one unit per triangle; every corner is shaded (Section 3.3,
+ *                 "Statically batched naive").
+ *  STATIC_BALLOT  batches of batch_tris triangles (Section 3.3); each batch
+ *                 is cut into rounds, the longest runs of whole triangles with
+ *                 at most 64 distinct indices (Algorithm 1 on a 64-lane
+ *                 wavefront); ids in first-occurrence order.
+ *  STATIC_SORT    static batches; local id = ascending rank among the batch's
+ *                 distinct indices (Algorithm 2 applied to a static batch).
+ *  STATIC_HASH    static batches; ids in first-occurrence order (Algorithm 3
+ *                 applied to a static batch).
+ *  DYN_SORT       dynamic batches (Section 3.4): the longest runs of whole
+ *                 triangles with at most max_unique distinct indices and at
+ *                 most batch_tris triangles; ascending-rank ids (Algorithm 2).
+ *  DYN_HASH       dynamic batches, LDS hash table (Algorithm 3), ids in
+ *                 first-occurrence order.
+ *  DYN_PHASH      dynamic batches, bounded per-lane probing then
+ *                 wavefront-cooperative probing (Section 3.4, "parallel
+ *                 hashing"); ids in first-occurrence order.
+ *  DYN_BALLOT     dynamic batches cut into ballot rounds as STATIC_BALLOT.
+ * Hash-table slot numbers depend on atomic races; exported ids never do.
+ */
+typedef enum {
+    VR_NAIVE = 0,
+    VR_STATIC_BALLOT = 1,
+    VR_STATIC_SORT = 2,
+    VR_STATIC_HASH = 3,
+    VR_DYN_SORT = 4,
+    VR_DYN_HASH = 5,
+    VR_DYN_PHASH = 6,
+    VR_DYN_BALLOT = 7
+} vr_strategy;
+
+/* Limits on batch_tris per strategy (argument error beyond them). */
+#define VR_MAX_BATCH_STATIC 256        /* STATIC_SORT, STATIC_HASH            */
+#define VR_MAX_BATCH_BALLOT 1024       /* STATIC_BALLOT                       */
+#define VR_MAX_BATCH_DYNAMIC 512       /* DYN_* (the triangle cap N_pmax)     */
+#define VR_MAX_UNIQUE 512              /* DYN_* unique budget N_u             */
+#define VR_MAX_INDICES 3221225469ull   /* num_indices < 3 * 2^30              */
+#define VR_MAX_LIGHTS 16
+
+typedef struct {
+    uint32_t max_unique;   /* N_u for DYN_*: 0 = 64*ceil(batch_tris/64) capped
+                              at 512, else 3..512.  Ignored by static modes.   */
+    uint32_t wg_size;      /* 0 = automatic, else a multiple of 64 <= 1024;
+                              changes launch shape only, never results.        */
+    uint32_t hash_slots;   /* 0 = automatic, else a power of two >= the unit's
+                              distinct bound (N_u, or 3*batch_tris) and <= 4096;
+                              never changes results.                            */
+    uint32_t hash_probes;  /* DYN_PHASH per-lane probes before the cooperative
+                              path: 0 = 4, else <= 64; never changes results.   */
+    const uint32_t *d_plan; /* DYN_*: a plan written by vr_plan_dynamic() with
+                              the same indices, max_unique and batch_tris, or
+                              NULL to build one on the context's stream.       */
+} vr_opts;
+
+typedef struct {
+    uint32_t kind;            /* 0 MVP, 1 PHONG, 2 OFFSET                       */
+    uint32_t num_lights;      /* PHONG: 0..16                                   */
+    uint32_t iterations;      /* OFFSET: refinement steps, <= 4096              */
+    uint32_t spec_squarings;  /* PHONG: specular exponent 2^s, s <= 8           */
+    float mvp[16];            /* row-major 4x4 applied to (p, 1)                */
+    float model[12];          /* row-major 3x4: world position for lighting     */
+    float normal[9];          /* row-major 3x3 normal matrix                    */
+    float eye[3];
+    float ambient[3];
+    float kd, ks, katt;       /* diffuse, specular, distance attenuation        */
+    float coef[8];            /* OFFSET: c0 c1 c2 c3 cvec.xyz, [7] unused       */
+    float lights[VR_MAX_LIGHTS][6]; /* position xyz, colour rgb                 */
+} vr_shader_params;
+
+/*
+ * Outputs of one draw (device pointers; any may be NULL).
+ *  corners           float[3T][12]: corner k of triangle t at row 3t+k, the
+ *                    shaded vertex of indices[3t+k] (the assembled triangle).
+ *  tris              uint32[3T]: tris[3t+k] = vbase(unit) + local id, an index
+ *                    into verts.
+ *  verts             float[verts_cap][12]: unit u's shaded vertices at rows
+ *                    vbase(u) .. vbase(u)+inv(u)-1, vbase = sum of earlier
+ *                    units' invocations.  verts_cap >= 3T when verts != NULL.
+ *  local_idx         uint16[3T]: the unit-local id of every corner.
+ *  unit_offsets      uint32[units_cap+1]: first triangle of every unit, then T.
+ *  unit_invocations  uint32[units_cap]: vertex-shader invocations per unit.
+ *                    units_cap >= T, or >= ceil(T/batch_tris) for
+ *                    STATIC_SORT / STATIC_HASH, when either unit array is set.
+ *  counters          uint64[4]: {invocations, units, 0, 0}, overwritten.
+ */
+typedef struct {
+    float *corners;
+    uint32_t *tris;
+    float *verts;
+    uint64_t verts_cap;
+    uint16_t *local_idx;
+    uint32_t *unit_offsets;
+    uint32_t *unit_invocations;
+    uint64_t units_cap;
+    uint64_t *counters;
+} vr_outputs;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Scratch memory is allocated on
+ * first use, grows as needed and is released by vr_destroy(). */
+vr_status vr_create(vr_ctx **ctx, int device, void *hip_stream);
+void vr_destroy(vr_ctx *ctx);
+/* Re-target the context to another stream of the same device. */
+vr_status vr_set_stream(vr_ctx *ctx, void *hip_stream);
+
+/* Host-only argument check used by every draw entry point: returns VR_OK,
+ * VR_ERR_ARG or VR_ERR_CAPACITY and touches no device. */
+vr_status vr_check_args(uint64_t num_indices, uint32_t num_vertices,
+                        const vr_shader_params *shader, vr_strategy strategy,
+                        uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out);
+
+/*
+ * Dynamic batching (Section 3.4): scan the triangles front to back and close
+ * a batch when adding the next triangle would exceed max_unique distinct
+ * indices or max_tris triangles.  Runs on the device.  Writes into d_plan
+ * (uint32[T+2], caller-owned): d_plan[0] = B, d_plan[1..B+1] = the batch
+ * start triangles followed by T.  plan_cap is the length of d_plan in
+ * elements and must be >= T+2.  max_unique in 3..512, max_tris in 1..512.
+ */
+vr_status vr_plan_dynamic(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_indices,
+                          uint32_t num_vertices, uint32_t max_unique, uint32_t max_tris,
+                          uint32_t *d_plan, uint64_t plan_cap);
+
+/*
+ * One draw: batch, deduplicate, shade each unit-unique vertex once with the
+ * vertex program in `shader`, and assemble the outputs described above
+ * (Algorithms 1-3, Section 4.2).  batch_tris is N_p for static strategies
+ * and the triangle cap for dynamic ones; NAIVE accepts any value >= 1.
+ * num_indices == 0 is valid and writes zero counters.  An out-of-range index
+ * is reported by the next vr_sync() as VR_ERR_INDEX_RANGE.
+ */
+vr_status vr_process_draw(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_indices,
+                          const float *d_vertices, uint32_t num_vertices,
+                          const vr_shader_params *shader, vr_strategy strategy,
+                          uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out);
+
+/* Wait for the context's stream.  Returns the first device-side error raised
+ * since the previous vr_sync (then clears it) and, when h_invocations is not
+ * NULL, the vertex-shader invocations of all draws since then. */
+vr_status vr_sync(vr_ctx *ctx, uint64_t *h_invocations);
+
+/* Text of the last error on ctx (or of the last vr_create failure when ctx
+ * is NULL).  Valid until the next call on the same context. */
+const char *vr_last_error(const vr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -65,7 +65,7 @@ int vro_check_args(uint64_t num_indices, uint32_t num_vertices, const vro_shader
 {
     (void)num_vertices;
     if (!sh || !out) return VRO_ERR_ARG;
-    if (num_indices % 3 != 0 || num_indices > 0xFFFFFFFFull) return VRO_ERR_ARG;
+    if (num_indices % 3 != 0 || num_indices > 3ull * ((1ull << 30) - 1)) return VRO_ERR_ARG;
     if (strategy < VRO_NAIVE || strategy > VRO_DYN_BALLOT) return VRO_ERR_ARG;
     if (batch_tris == 0 || batch_tris > max_batch_tris(strategy)) return VRO_ERR_ARG;
     if (sh->kind > 2 || sh->num_lights > VRO_MAX_LIGHTS || sh->spec_squarings > 8 ||
@@ -450,8 +450,9 @@ int vro_process_draw(const uint32_t *idx, uint64_t num_indices, const float *ver
             }
             for (uint64_t k = 0; k < ncorner; ++k) local[k] = set.slot[ui[k]];
         }
-        for (uint32_t j = 0; j < inv; ++j)
-            vro_shade(sh, vertices + (uint64_t)VRO_IN_FLOATS * uniq[j], sv + (uint64_t)VRO_OUT_FLOATS * j);
+        if (out->verts || out->corners)
+            for (uint32_t j = 0; j < inv; ++j)
+                vro_shade(sh, vertices + (uint64_t)VRO_IN_FLOATS * uniq[j], sv + (uint64_t)VRO_OUT_FLOATS * j);
         if (out->verts)
             memcpy(out->verts + VRO_OUT_FLOATS * vbase, sv, sizeof(float) * VRO_OUT_FLOATS * inv);
         for (uint64_t k = 0; k < ncorner; ++k) {

@@ -1,0 +1,202 @@
+// Device-side building blocks of the geometry stage for gfx950 (wave64):
+// vertex programs, wavefront and workgroup scans, look-back prefix.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vr.h"
+
+namespace vr {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;   // empty hash slot / no index
+constexpr int kWave = 64;
+constexpr int kOutF4 = 3;                  // a shaded vertex is 3 float4 (48 B)
+
+// Multiplicative hashing of a vertex index into a table of 2^bits slots.
+__device__ __forceinline__ uint32_t hash_slot(uint32_t key, uint32_t bits) {
+    return (key * 0x9E3779B1u) >> (32u - bits);
+}
+
+// Kernel-side error bits (a vr_status value is stored, first one wins).
+__device__ __forceinline__ void raise_error(uint32_t *err, uint32_t code) {
+    atomicCAS(err, 0u, code);
+}
+
+// --------------------------------------------------------------------------
+// Vertex programs.  Every operation is spelled out (fma = single rounding,
+// '/' and sqrtf correctly rounded, contraction disabled at build time) so the
+// FP32 results are the ones fixed by the written program.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, float by, float bz) {
+    return __builtin_fmaf(az, bz, __builtin_fmaf(ay, by, ax * bx));
+}
+
+// row r of a row-major matrix with 4 columns, applied to (x, y, z, 1)
+__device__ __forceinline__ float xrow(const float *M, int r, float x, float y, float z) {
+    return __builtin_fmaf(M[4 * r + 2], z,
+                          __builtin_fmaf(M[4 * r + 1], y, __builtin_fmaf(M[4 * r + 0], x, M[4 * r + 3])));
+}
+
+__device__ __forceinline__ void normalize3(float &x, float &y, float &z) {
+    float s = dot3(x, y, z, x, y, z);
+    float q = 1.0f / __builtin_sqrtf(s);
+    x = x * q;
+    y = y * q;
+    z = z * q;
+}
+
+// in: a = (px, py, pz, nx), b = (ny, nz, u, v); out: 3 float4 =
+// (clip xyzw), (n'xyz, u), (v, rgb)
+template <int KIND>
+__device__ __forceinline__ void shade_vertex(const vr_shader_params &sh, float4 a, float4 b,
+                                             float4 &o0, float4 &o1, float4 &o2) {
+    float px = a.x, py = a.y, pz = a.z;
+    const float nx = a.w, ny = b.x, nz = b.y;
+    if (KIND == 2) {
+        const float *c = sh.coef;
+        const float ph = dot3(c[4], c[5], c[6], px, py, pz);
+        float h = 0.0f;
+        for (uint32_t it = 0; it < sh.iterations; ++it) {
+            float g = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(c[3], h, c[2]), h, c[1]), h, ph);
+            h = __builtin_fmaf(c[0], g - h, h);
+        }
+        px = __builtin_fmaf(h, nx, px);
+        py = __builtin_fmaf(h, ny, py);
+        pz = __builtin_fmaf(h, nz, pz);
+    }
+    o0.x = xrow(sh.mvp, 0, px, py, pz);
+    o0.y = xrow(sh.mvp, 1, px, py, pz);
+    o0.z = xrow(sh.mvp, 2, px, py, pz);
+    o0.w = xrow(sh.mvp, 3, px, py, pz);
+    float mx = dot3(sh.normal[0], sh.normal[1], sh.normal[2], nx, ny, nz);
+    float my = dot3(sh.normal[3], sh.normal[4], sh.normal[5], nx, ny, nz);
+    float mz = dot3(sh.normal[6], sh.normal[7], sh.normal[8], nx, ny, nz);
+    normalize3(mx, my, mz);
+    float cr = sh.ambient[0], cg = sh.ambient[1], cb = sh.ambient[2];
+    if (KIND == 1) {
+        const float wx = xrow(sh.model, 0, px, py, pz);
+        const float wy = xrow(sh.model, 1, px, py, pz);
+        const float wz = xrow(sh.model, 2, px, py, pz);
+        float vx = sh.eye[0] - wx, vy = sh.eye[1] - wy, vz = sh.eye[2] - wz;
+        normalize3(vx, vy, vz);
+        for (uint32_t l = 0; l < sh.num_lights; ++l) {
+            const float *L = sh.lights[l];
+            const float dx = L[0] - wx, dy = L[1] - wy, dz = L[2] - wz;
+            const float d2 = dot3(dx, dy, dz, dx, dy, dz);
+            const float inv = 1.0f / __builtin_sqrtf(d2);
+            const float lx = dx * inv, ly = dy * inv, lz = dz * inv;
+            const float ndl = dot3(mx, my, mz, lx, ly, lz);
+            const float df = ndl > 0.0f ? ndl : 0.0f;
+            const float t = 2.0f * ndl;
+            const float rx = __builtin_fmaf(t, mx, -lx);
+            const float ry = __builtin_fmaf(t, my, -ly);
+            const float rz = __builtin_fmaf(t, mz, -lz);
+            const float rv = dot3(rx, ry, rz, vx, vy, vz);
+            float sp = rv > 0.0f ? rv : 0.0f;
+            for (uint32_t s = 0; s < sh.spec_squarings; ++s) sp = sp * sp;
+            const float att = 1.0f / __builtin_fmaf(sh.katt, d2, 1.0f);
+            const float k = att * __builtin_fmaf(sh.ks, sp, sh.kd * df);
+            cr = __builtin_fmaf(k, L[3], cr);
+            cg = __builtin_fmaf(k, L[4], cg);
+            cb = __builtin_fmaf(k, L[5], cb);
+        }
+    }
+    o1 = make_float4(mx, my, mz, b.z);
+    o2 = make_float4(b.w, cr, cg, cb);
+}
+
+// --------------------------------------------------------------------------
+// Wavefront / workgroup helpers (wave64)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t u = __shfl_up(v, d, kWave);
+        if (lane >= (uint32_t)d) v += u;
+    }
+    return v;
+}
+
+// Exclusive scan over one value per thread of an NT-thread workgroup.
+// `tmp` is LDS scratch of NT/64 words.  Contains barriers: call uniformly.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, uint32_t &total) {
+    constexpr int NW = NT / kWave;
+    const uint32_t tid = threadIdx.x, w = tid / kWave, lane = lane_id();
+    uint32_t incl = wave_incl_scan(v);
+    if (NW == 1) {
+        total = __shfl(incl, kWave - 1, kWave);
+        return incl - v;
+    }
+    if (lane == kWave - 1) tmp[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        uint32_t t = tmp[i];
+        before += (i < (int)w) ? t : 0u;
+        all += t;
+    }
+    __syncthreads();
+    total = all;
+    return before + incl - v;
+}
+
+// --------------------------------------------------------------------------
+// Single-pass prefix over units (decoupled look-back).  A status word is
+//   [63:62] flag (0 = not ready, 1 = aggregate, 2 = inclusive prefix)
+//   [61:32] unit count, [31:0] invocation count
+// so both prefixes travel in one 64-bit word; totals stay below 2^30 units
+// and 2^32 invocations because a draw has fewer than 2^30 triangles.
+// --------------------------------------------------------------------------
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagInc = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+
+__device__ __forceinline__ void status_store(unsigned long long *p, uint64_t v) {
+    __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t status_load(unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publishes unit b's aggregate; called by one thread.
+__device__ __forceinline__ void lookback_publish(unsigned long long *status, uint32_t b, uint64_t agg) {
+    status_store(&status[b], (b == 0 ? kFlagInc : kFlagAgg) | agg);
+}
+
+// Returns the exclusive prefix of unit b (packed), called by one thread
+// after lookback_publish.  Waits on predecessors, which hold lower tickets
+// and therefore already run; a bounded spin turns a lost update into an
+// error instead of a hang.
+__device__ __forceinline__ uint64_t lookback_resolve(unsigned long long *status, uint32_t b, uint64_t agg,
+                                                     uint32_t *err) {
+    if (b == 0) return 0;
+    uint64_t excl = 0;
+    int64_t j = (int64_t)b - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+        uint64_t s = status_load(&status[j]);
+        if ((s >> 62) == 0) {
+            if (++spins > (1u << 26)) {
+                raise_error(err, VR_ERR_DEVICE);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += s & kValMask;
+        if (s & kFlagInc) break;
+        --j;
+    }
+    status_store(&status[b], kFlagInc | (excl + agg));
+    return excl;
+}
+
+}  // namespace vr

@@ -1,0 +1,565 @@
+// Geometry-stage kernels for gfx950: naive, LDS sort / hash / parallel-hash
+// deduplication over static or dynamic batches, and wave64 ballot rounds.
+#pragma once
+
+#include "vr_device.h"
+
+namespace vr {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+enum DedupMode { kSort = 0, kHash = 1, kPHash = 2 };
+
+// Everything a draw kernel reads besides the shader parameters.
+struct DrawArgs {
+    const uint32_t *idx;        // uint32[3T]
+    const f4 *vtx;              // [V][2] float4
+    uint32_t V, T;
+    uint32_t batch_tris;        // static batches: N_p
+    uint32_t num_batches;       // static batches: ceil(T / N_p)
+    const uint32_t *plan;       // dynamic batches: [B, start_0 .. start_{B-1}, T]
+    f4 *corners;                // [3T][3]
+    uint32_t *tris;             // [3T]
+    f4 *verts;                  // [..][3]
+    uint16_t *local_idx;        // [3T]
+    uint32_t *unit_offsets;     // [units + 1]
+    uint32_t *unit_inv;         // [units]
+    unsigned long long *counters;   // [4]
+    uint32_t *ticket;           // work counter, zeroed per launch
+    unsigned long long *status; // look-back words, zeroed per launch
+    uint32_t *err;              // first device-side error
+    unsigned long long *total_inv;  // invocations since the last vr_sync
+    uint32_t hash_bits;         // log2 of the LDS hash-table size
+    uint32_t probes;            // parallel hashing: per-lane probes
+    uint32_t max_idx;           // LDS capacity in corners (3 * max triangles per unit)
+    uint32_t max_uniq;          // LDS capacity in shaded vertices
+    uint32_t need_prefix;       // tris / verts / unit arrays requested
+    uint32_t status_cap;        // look-back words available
+};
+
+// Units a launch may take: the plan's count, bounded by the look-back
+// capacity (a plan built for other limits raises an error instead of
+// overrunning scratch).
+__device__ __forceinline__ uint32_t launch_units(const DrawArgs &A, uint32_t nb) {
+    if (A.need_prefix && nb > A.status_cap) {
+        raise_error(A.err, VR_ERR_CAPACITY);
+        return A.status_cap;
+    }
+    return nb;
+}
+
+__device__ __forceinline__ uint32_t batch_count(const DrawArgs &A) {
+    return A.plan ? A.plan[0] : A.num_batches;
+}
+
+__device__ __forceinline__ void batch_range(const DrawArgs &A, uint32_t b, uint32_t &t0, uint32_t &t1) {
+    if (A.plan) {
+        t0 = A.plan[1 + b];
+        t1 = A.plan[2 + b];
+    } else {
+        t0 = b * A.batch_tris;
+        t1 = min(A.T, t0 + A.batch_tris);
+    }
+}
+
+// Index fetch with the range check fused in: an index >= V raises
+// VR_ERR_INDEX_RANGE and is replaced by 0 so no access leaves the buffers.
+__device__ __forceinline__ uint32_t fetch_index(const DrawArgs &A, uint64_t pos) {
+    uint32_t k = A.idx[pos];
+    if (k >= A.V) {
+        raise_error(A.err, VR_ERR_INDEX_RANGE);
+        k = 0;
+    }
+    return k;
+}
+
+template <int KIND>
+__device__ __forceinline__ void shade_to_lds(const DrawArgs &A, const vr_shader_params &sh, uint32_t v,
+                                             f4 *dst) {
+    const f4 a = A.vtx[2ull * v], b = A.vtx[2ull * v + 1];
+    float4 o0, o1, o2;
+    shade_vertex<KIND>(sh, make_float4(a.x, a.y, a.z, a.w), make_float4(b.x, b.y, b.z, b.w), o0, o1, o2);
+    dst[0] = f4{o0.x, o0.y, o0.z, o0.w};
+    dst[1] = f4{o1.x, o1.y, o1.z, o1.w};
+    dst[2] = f4{o2.x, o2.y, o2.z, o2.w};
+}
+
+// Assembly (Section 4.2): every corner of the unit's triangles receives its
+// shaded vertex.  The unit's corner rows are one contiguous span, so lane q
+// stores float4 q of the span: fully coalesced 16-byte stores.
+template <int NT, typename LocalT>
+__device__ __forceinline__ void write_unit(const DrawArgs &A, uint32_t t0, uint32_t ntri, const LocalT *s_local,
+                                           const f4 *s_sv, uint32_t inv, uint32_t vbase, uint32_t unit) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t ncorner = 3 * ntri;
+    if (A.corners) {
+        f4 *dst = A.corners + 9ull * t0;
+        const uint32_t cnt = 9 * ntri;
+        for (uint32_t q = tid; q < cnt; q += NT) {
+            const uint32_t k = q / 3, part = q - 3 * k;
+            __builtin_nontemporal_store(s_sv[3 * (uint32_t)s_local[k] + part], dst + q);
+        }
+    }
+    if (A.tris || A.local_idx) {
+        for (uint32_t k = tid; k < ncorner; k += NT) {
+            const uint32_t l = s_local[k];
+            if (A.tris) A.tris[3ull * t0 + k] = vbase + l;
+            if (A.local_idx) A.local_idx[3ull * t0 + k] = (uint16_t)l;
+        }
+    }
+    if (A.verts) {
+        f4 *dst = A.verts + 3ull * vbase;
+        for (uint32_t q = tid; q < 3 * inv; q += NT) __builtin_nontemporal_store(s_sv[q], dst + q);
+    }
+    if (tid == 0) {
+        if (A.unit_offsets) A.unit_offsets[unit] = t0;
+        if (A.unit_inv) A.unit_inv[unit] = inv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-launch reset of the work counter, counters and look-back words.
+// ---------------------------------------------------------------------------
+__global__ void k_reset(uint32_t *ticket, unsigned long long *counters, unsigned long long *status,
+                        uint32_t n_status, const uint32_t *plan) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n = plan ? min(n_status, plan[0]) : n_status;
+    if (i < n) status[i] = 0;
+    if (i == 0) *ticket = 0;
+    if (counters && i < 4) counters[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Naive (Section 3.3): no reuse, every corner is shaded.  One lane per
+// corner (three invocations per triangle as in the paper's one thread per
+// triangle); the block's corner rows are staged in LDS and stored
+// contiguously.
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(256) void k_naive(DrawArgs A, vr_shader_params sh) {
+    __shared__ f4 s_sv[256 * 3];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t n = 3ull * A.T;
+    const uint64_t c0 = (uint64_t)blockIdx.x * 256;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(256, n - c0);
+    if (tid < cnt) {
+        const uint64_t c = c0 + tid;
+        const uint32_t v = fetch_index(A, c);
+        shade_to_lds<KIND>(A, sh, v, s_sv + 3 * tid);
+        const uint32_t corner = (uint32_t)(c % 3);
+        if (A.tris) A.tris[c] = (uint32_t)c;
+        if (A.local_idx) A.local_idx[c] = (uint16_t)corner;
+        if (corner == 0) {
+            const uint32_t t = (uint32_t)(c / 3);
+            if (A.unit_offsets) A.unit_offsets[t] = t;
+            if (A.unit_inv) A.unit_inv[t] = 3;
+        }
+    }
+    __syncthreads();
+    for (uint32_t q = tid; q < 3 * cnt; q += 256) {
+        if (A.corners) __builtin_nontemporal_store(s_sv[q], A.corners + 3 * c0 + q);
+        if (A.verts) __builtin_nontemporal_store(s_sv[q], A.verts + 3 * c0 + q);
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        if (A.unit_offsets) A.unit_offsets[A.T] = A.T;
+        if (A.counters) {
+            A.counters[0] = n;
+            A.counters[1] = A.T;
+        }
+        atomicAdd(A.total_inv, (unsigned long long)n);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS layout of the dedup kernel (bytes), shared with the host launcher.
+// ---------------------------------------------------------------------------
+struct DedupLds {
+    uint32_t keys, local, pairs, table, first, uniq, sv, tmp, total;
+};
+
+__host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
+
+__host__ __device__ inline uint32_t pow2_ceil(uint32_t x) {
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+__host__ __device__ inline DedupLds dedup_lds_layout(int mode, uint32_t max_idx, uint32_t max_uniq,
+                                                     uint32_t hash_bits) {
+    DedupLds L{};
+    uint32_t off = 0;
+    L.keys = off;  off += align16(4 * max_idx);
+    L.local = off; off += align16(4 * max_idx);
+    if (mode == kSort) {
+        L.pairs = off; off += 8 * pow2_ceil(max_idx);
+        L.table = L.first = 0;
+    } else {
+        L.pairs = 0;
+        L.table = off; off += align16(4u << hash_bits);
+        L.first = off; off += align16(4u << hash_bits);
+    }
+    L.uniq = off; off += align16(4 * max_uniq);
+    L.sv = off;   off += 48 * max_uniq;
+    L.tmp = off;  off += 64;
+    L.total = off;
+    return L;
+}
+
+// Bitonic sort of n2 (a power of two) 64-bit keys in LDS.
+template <int NT>
+__device__ __forceinline__ void lds_bitonic_sort(unsigned long long *a, uint32_t n2) {
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < n2 / 2; i += NT) {
+                const uint32_t lo = 2 * i - (i & (j - 1));
+                const uint32_t hi = lo + j;
+                const bool up = (lo & k) == 0;
+                const unsigned long long x = a[lo], y = a[hi];
+                if ((x > y) == up) {
+                    a[lo] = y;
+                    a[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Ranks flagged entries of a unit in index order with a blocked scan:
+// thread t owns entries [t*E, t*E+E).  flag(i) is evaluated once and kept
+// in a register mask (E <= 32).  Returns the number of flagged entries.
+template <int NT, typename FlagF, typename EmitF>
+__device__ __forceinline__ uint32_t rank_flagged(uint32_t n, uint32_t *s_tmp, FlagF flag, EmitF emit) {
+    const uint32_t E = (n + NT - 1) / NT;
+    const uint32_t lo = min(n, threadIdx.x * E), hi = min(n, lo + E);
+    uint32_t mask = 0, cnt = 0;
+    for (uint32_t i = lo; i < hi; ++i)
+        if (flag(i)) {
+            mask |= 1u << (i - lo);
+            ++cnt;
+        }
+    uint32_t total;
+    uint32_t r = block_excl_scan<NT>(cnt, s_tmp, total);   // has barriers
+    for (uint32_t i = lo; i < hi; ++i)
+        if (mask & (1u << (i - lo))) emit(i, r++);
+    return total;
+}
+
+// ---------------------------------------------------------------------------
+// Batched deduplication + shading + assembly (Algorithms 2 and 3, and the
+// parallel-hashing variant).  Persistent workgroups take units in ticket
+// order; a unit of n corners is deduplicated in LDS into inv unique
+// vertices with canonical local ids:
+//   sort  - ascending rank among distinct indices (Algorithm 2),
+//   hash  - first-occurrence order (Algorithm 3, ids made independent of
+//           the insertion races by ranking each slot's first position),
+//   phash - as hash, but a lane that fails `probes` linear probes hands its
+//           key to a wavefront-cooperative probe of 64 slots at a time.
+// ---------------------------------------------------------------------------
+template <int NT, int MODE, int KIND>
+__global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const DedupLds L = dedup_lds_layout(MODE, A.max_idx, A.max_uniq, A.hash_bits);
+    uint32_t *s_keys = (uint32_t *)(smem + L.keys);
+    uint32_t *s_local = (uint32_t *)(smem + L.local);
+    uint32_t *s_uniq = (uint32_t *)(smem + L.uniq);
+    f4 *s_sv = (f4 *)(smem + L.sv);
+    uint32_t *s_tmp = (uint32_t *)(smem + L.tmp);
+    __shared__ uint32_t s_unit, s_vbase;
+
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t nb = launch_units(A, batch_count(A));
+    unsigned long long my_inv = 0;
+    for (;;) {
+        if (tid == 0) s_unit = atomicAdd(A.ticket, 1u);
+        __syncthreads();
+        const uint32_t u = s_unit;
+        if (u >= nb) break;
+        uint32_t t0, t1;
+        batch_range(A, u, t0, t1);
+        uint32_t n = 3 * (t1 - t0);
+        const bool fits = t1 >= t0 && n <= A.max_idx;   // false only for a plan built with other limits
+        if (!fits) {
+            if (tid == 0) raise_error(A.err, VR_ERR_CAPACITY);
+            n = 0;
+        }
+
+        for (uint32_t i = tid; i < n; i += NT) s_keys[i] = fetch_index(A, 3ull * t0 + i);
+
+        uint32_t inv;
+        if (MODE == kSort) {
+            unsigned long long *s_pairs = (unsigned long long *)(smem + L.pairs);
+            const uint32_t n2 = pow2_ceil(max(n, 2u));
+            __syncthreads();
+            for (uint32_t i = tid; i < n2; i += NT)
+                s_pairs[i] = i < n ? ((unsigned long long)s_keys[i] << 32) | i : ~0ull;
+            __syncthreads();
+            lds_bitonic_sort<NT>(s_pairs, n2);
+            // run ends of the sorted keys; the exclusive prefix over run ends
+            // is the rank of every entry's run (Algorithm 2's marks / prefix)
+            const uint32_t E = (n + NT - 1) / NT;
+            const uint32_t lo = min(n, tid * E), hi = min(n, lo + E);
+            uint32_t cnt = 0;
+            for (uint32_t i = lo; i < hi; ++i)
+                cnt += (i + 1 == n || (uint32_t)(s_pairs[i] >> 32) != (uint32_t)(s_pairs[i + 1] >> 32));
+            uint32_t r = block_excl_scan<NT>(cnt, s_tmp, inv);
+            for (uint32_t i = lo; i < hi; ++i) {
+                const unsigned long long p = s_pairs[i];
+                s_local[(uint32_t)p] = r;
+                if (i + 1 == n || (uint32_t)(p >> 32) != (uint32_t)(s_pairs[i + 1] >> 32))
+                    s_uniq[r++] = (uint32_t)(p >> 32);
+            }
+        } else {
+            uint32_t *s_table = (uint32_t *)(smem + L.table);
+            uint32_t *s_first = (uint32_t *)(smem + L.first);
+            const uint32_t S = 1u << A.hash_bits, mask = S - 1;
+            for (uint32_t s = tid; s < S; s += NT) {
+                s_table[s] = kEmpty;
+                s_first[s] = kEmpty;
+            }
+            __syncthreads();
+            if (MODE == kHash) {
+                for (uint32_t i = tid; i < n; i += NT) {
+                    const uint32_t k = s_keys[i];
+                    uint32_t p = hash_slot(k, A.hash_bits);
+                    for (uint32_t probe = 0;; ++probe) {   // linear probing; S >= distinct keys
+                        const uint32_t prev = atomicCAS(&s_table[p], kEmpty, k);
+                        if (prev == kEmpty || prev == k) break;
+                        if (probe >= mask) {              // table full: only with foreign plans
+                            raise_error(A.err, VR_ERR_CAPACITY);
+                            break;
+                        }
+                        p = (p + 1) & mask;
+                    }
+                    s_local[i] = p;
+                    atomicMin(&s_first[p], i);
+                }
+            } else {
+                // wave-uniform sweep so the cooperative path sees every lane
+                for (uint32_t base = (tid / kWave) * kWave; base < n; base += NT) {
+                    const uint32_t i = base + lane;
+                    const bool act = i < n;
+                    const uint32_t k = act ? s_keys[i] : 0u;
+                    uint32_t p = hash_slot(k, A.hash_bits);
+                    uint32_t slot = 0;
+                    bool placed = !act;
+                    for (uint32_t r = 0; r < A.probes && !placed; ++r) {
+                        const uint32_t prev = atomicCAS(&s_table[p], kEmpty, k);
+                        if (prev == kEmpty || prev == k) {
+                            slot = p;
+                            placed = true;
+                        } else {
+                            p = (p + 1) & mask;
+                        }
+                    }
+                    uint64_t pend = ballot(!placed);
+                    while (pend) {
+                        const uint32_t Lr = (uint32_t)__ffsll((long long)pend) - 1;
+                        const uint32_t key = __builtin_amdgcn_readlane(k, Lr);
+                        uint32_t start = __builtin_amdgcn_readlane(p, Lr);
+                        for (uint32_t sweep = 0;; ++sweep) {
+                            if (sweep > 2 * (mask + 1)) {     // table full: only with foreign plans
+                                if (lane == 0) raise_error(A.err, VR_ERR_CAPACITY);
+                                break;
+                            }
+                            const uint32_t s = (start + lane) & mask;
+                            const uint32_t val = __hip_atomic_load(&s_table[s], __ATOMIC_RELAXED,
+                                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                            const uint64_t hit = ballot(val == kEmpty || val == key);
+                            if (!hit) {
+                                start = (start + kWave) & mask;
+                                continue;
+                            }
+                            const uint32_t w = (uint32_t)__ffsll((long long)hit) - 1;
+                            const uint32_t ws = (start + w) & mask;
+                            uint32_t got = 0;
+                            if (lane == w) got = atomicCAS(&s_table[ws], kEmpty, key);
+                            got = __builtin_amdgcn_readlane(got, w);
+                            if (got == kEmpty || got == key) {
+                                if (lane == Lr) {
+                                    slot = ws;
+                                    placed = true;
+                                }
+                                break;
+                            }
+                            start = ws;   // lost the slot to another key: continue past it
+                        }
+                        pend &= pend - 1;
+                    }
+                    if (act) {
+                        s_local[i] = slot;
+                        atomicMin(&s_first[slot], i);
+                    }
+                }
+            }
+            __syncthreads();
+            // canonical ids: a slot's id is the rank of its first position
+            inv = rank_flagged<NT>(
+                n, s_tmp, [&](uint32_t i) { return s_first[s_local[i]] == i; },
+                [&](uint32_t i, uint32_t r) {
+                    s_uniq[r] = s_keys[i];
+                    s_keys[i] = r;   // stash the rank; the slot is rewritten below
+                });
+            __syncthreads();
+            // first positions now carry ranks
+            for (uint32_t i = tid; i < n; i += NT)
+                if (s_first[s_local[i]] == i) s_first[s_local[i]] = s_keys[i] | 0x80000000u;
+            __syncthreads();
+            for (uint32_t i = tid; i < n; i += NT) s_local[i] = s_first[s_local[i]] & 0x7FFFFFFFu;
+        }
+
+        if (inv > A.max_uniq) {   // only with a plan built for a larger N_u
+            if (tid == 0) raise_error(A.err, VR_ERR_CAPACITY);
+            inv = 0;
+        }
+        // publish this unit's invocation count early; resolve after shading
+        if (A.need_prefix && tid == 0) lookback_publish(A.status, u, (1ull << 32) | inv);
+        __syncthreads();
+        for (uint32_t j = tid; j < inv; j += NT) shade_to_lds<KIND>(A, sh, s_uniq[j], s_sv + 3 * j);
+        if (tid == 0) {
+            uint32_t vb = 0;
+            if (A.need_prefix) vb = (uint32_t)lookback_resolve(A.status, u, (1ull << 32) | inv, A.err);
+            s_vbase = vb;
+            if (A.unit_offsets && u + 1 == nb) A.unit_offsets[nb] = A.T;
+        }
+        __syncthreads();
+        if (fits && (inv > 0 || n == 0)) write_unit<NT>(A, t0, t1 - t0, s_local, s_sv, inv, s_vbase, u);
+        if (tid == 0) my_inv += inv;
+        __syncthreads();
+    }
+    if (tid == 0 && my_inv) {
+        atomicAdd(A.total_inv, my_inv);
+        if (A.counters) atomicAdd(&A.counters[0], my_inv);
+    }
+    if (blockIdx.x == 0 && tid == 0 && A.counters) atomicAdd(&A.counters[1], (unsigned long long)nb);
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 ballot rounds (Algorithm 1 on a 64-lane wavefront).  One wavefront
+// owns a batch and cuts it into rounds: it fetches 21 whole triangles (63
+// indices, one per lane) at a time and resolves them one distinct value at
+// a time: the lowest unresolved lane's index is broadcast (readlane), every
+// lane holding the same index is resolved together (ballot), and if no lane
+// holds it yet the lowest free lane takes it.  The first triangle that would
+// need a 65th lane ends the round; lanes taken by rejected triangles are
+// released, so a round shades exactly its distinct indices.
+// ---------------------------------------------------------------------------
+struct RoundState {
+    uint32_t my_id;   // the vertex this lane shades in the round
+    uint32_t fill;    // lanes in use (= invocations of the round)
+};
+
+// Processes one round starting at triangle `cur`; returns the round's end.
+// When s_map is not NULL it receives each corner's lane (local id).
+__device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t cur, uint32_t t1,
+                                                 uint8_t *s_map, RoundState &st) {
+    const uint32_t lane = lane_id();
+    uint32_t my_id = kEmpty, my_intro = kEmpty, fill = 0, done = 0;
+    for (;;) {
+        const uint32_t gt = min(21u, t1 - cur);
+        const uint32_t nc = 3 * gt;
+        const bool act = lane < nc;
+        const uint32_t k = act ? fetch_index(A, 3ull * cur + lane) : kEmpty;
+        uint64_t pend = ballot(act);
+        uint32_t slot = 0, f = fill;
+        while (pend) {
+            const uint32_t i = (uint32_t)__ffsll((long long)pend) - 1;
+            const uint32_t cv = __builtin_amdgcn_readlane(k, i);
+            const uint64_t same = ballot(k == cv) & pend;
+            const uint64_t own = ballot(my_id == cv);
+            uint32_t s;
+            if (own) {
+                s = (uint32_t)__ffsll((long long)own) - 1;
+            } else {
+                s = f;
+                if (lane == f) {
+                    my_id = cv;
+                    my_intro = done + i;
+                }
+                ++f;
+            }
+            if ((same >> lane) & 1ull) slot = s;
+            pend &= ~same;
+        }
+        const uint64_t bad = ballot(act && slot >= (uint32_t)kWave);
+        const uint32_t acc = bad ? ((uint32_t)__ffsll((long long)bad) - 1) / 3 : gt;
+        if (s_map && lane < 3 * acc) s_map[done + lane] = (uint8_t)slot;
+        done += 3 * acc;
+        cur += acc;
+        if (bad) {
+            const uint64_t keep = ballot(my_intro < done);
+            fill = (uint32_t)__popcll(keep);
+            if (!((keep >> lane) & 1ull)) my_id = kEmpty;
+            break;
+        }
+        fill = f;
+        if (cur >= t1) break;
+    }
+    st.my_id = my_id;
+    st.fill = fill;
+    return cur;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(64) void k_ballot(DrawArgs A, vr_shader_params sh) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    f4 *s_sv = (f4 *)smem;                    // 64 shaded vertices
+    uint8_t *s_map = smem + 64 * 48;          // local id per corner of a round
+    const uint32_t lane = lane_id();
+    const uint32_t nb = launch_units(A, batch_count(A));
+    unsigned long long my_inv = 0, my_units = 0;
+    for (;;) {
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(A.ticket, 1u);
+        b = __builtin_amdgcn_readfirstlane(b);
+        if (b >= nb) break;
+        uint32_t t0, t1;
+        batch_range(A, b, t0, t1);
+        if (t1 < t0 || 3 * (t1 - t0) > A.max_idx) {   // only with a plan built for other limits
+            if (lane == 0) raise_error(A.err, VR_ERR_CAPACITY);
+            t1 = t0;
+        }
+        uint32_t vbase = 0, ubase = b;
+        RoundState st;
+        if (A.need_prefix) {
+            // counting sweep: the batch's rounds and invocations, published
+            // before any output so later batches can resolve their prefix
+            uint32_t rounds = 0, inv = 0;
+            for (uint32_t cur = t0; cur < t1; ++rounds) {
+                cur = ballot_round(A, cur, t1, nullptr, st);
+                inv += st.fill;
+            }
+            uint64_t ex = 0;
+            if (lane == 0) {
+                const uint64_t agg = ((uint64_t)rounds << 32) | inv;
+                lookback_publish(A.status, b, agg);
+                ex = lookback_resolve(A.status, b, agg, A.err);
+            }
+            vbase = __builtin_amdgcn_readfirstlane((uint32_t)ex);
+            ubase = __builtin_amdgcn_readfirstlane((uint32_t)((ex >> 32) & 0x3FFFFFFFu));
+        }
+        uint32_t r = 0;
+        for (uint32_t cur = t0; cur < t1; ++r) {
+            const uint32_t end = ballot_round(A, cur, t1, s_map, st);
+            if (lane < st.fill) shade_to_lds<KIND>(A, sh, st.my_id, s_sv + 3 * lane);
+            __syncthreads();
+            write_unit<64>(A, cur, end - cur, s_map, s_sv, st.fill, vbase, ubase + r);
+            __syncthreads();
+            vbase += st.fill;
+            my_inv += st.fill;
+            cur = end;
+        }
+        my_units += r;
+        if (A.unit_offsets && b + 1 == nb && lane == 0) A.unit_offsets[ubase + r] = A.T;
+    }
+    if (lane == 0) {
+        if (my_inv) atomicAdd(A.total_inv, my_inv);
+        if (A.counters && my_inv) {
+            atomicAdd(&A.counters[0], my_inv);
+            atomicAdd(&A.counters[1], my_units);
+        }
+    }
+}
+
+}  // namespace vr

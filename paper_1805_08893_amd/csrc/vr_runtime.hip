@@ -1,0 +1,489 @@
+// Host runtime of the geometry stage: the C ABI declared in include/vr.h.
+// Validates arguments, owns per-context device scratch (grow-only), builds
+// dynamic batch plans on the device and dispatches the draw kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "vr.h"
+#include "vr_kernels.h"
+#include "vr_plan.h"
+
+using namespace vr;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// Device words owned by a context: error code, work ticket, and the
+// invocation total since the last vr_sync.
+struct CtxWords {
+    uint32_t err;
+    uint32_t ticket;
+    unsigned long long total_inv;
+};
+
+struct Scratch {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct vr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cus = 256;
+    size_t lds_limit = 65536;
+    std::string error;
+    CtxWords *d_words = nullptr;
+    Scratch status, plan, plan_work;
+    uint32_t host_err = 0;   // data error found on the host, reported by vr_sync
+};
+
+namespace {
+
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+        if (prev_ != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev_ >= 0) (void)hipSetDevice(prev_);
+    }
+
+  private:
+    int prev_ = -1;
+};
+
+vr_status fail(vr_ctx *c, vr_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->error = buf;
+    else g_create_error = buf;
+    return s;
+}
+
+#define VR_HIP(ctx, call)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return fail((ctx), VR_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Grow-only scratch.  The stream is drained before a buffer is replaced
+// because enqueued kernels may still use the old one.
+vr_status ensure(vr_ctx *c, Scratch &s, size_t bytes) {
+    if (bytes <= s.bytes) return VR_OK;
+    bytes = std::max<size_t>(bytes, 2 * s.bytes);
+    if (s.ptr) {
+        VR_HIP(c, hipStreamSynchronize(c->stream));
+        VR_HIP(c, hipFree(s.ptr));
+        s.ptr = nullptr;
+        s.bytes = 0;
+    }
+    if (hipMalloc(&s.ptr, bytes) != hipSuccess) {
+        s.ptr = nullptr;
+        return fail(c, VR_ERR_OOM, "scratch allocation of %zu bytes failed", bytes);
+    }
+    s.bytes = bytes;
+    return VR_OK;
+}
+
+bool is_dynamic(vr_strategy s) { return s >= VR_DYN_SORT && s <= VR_DYN_BALLOT; }
+bool is_ballot(vr_strategy s) { return s == VR_STATIC_BALLOT || s == VR_DYN_BALLOT; }
+
+uint32_t batch_limit(vr_strategy s) {
+    switch (s) {
+    case VR_NAIVE: return 0xFFFFFFFFu;
+    case VR_STATIC_BALLOT: return VR_MAX_BATCH_BALLOT;
+    case VR_STATIC_SORT:
+    case VR_STATIC_HASH: return VR_MAX_BATCH_STATIC;
+    default: return VR_MAX_BATCH_DYNAMIC;
+    }
+}
+
+uint32_t default_max_unique(uint32_t batch_tris) {
+    return std::min<uint32_t>(VR_MAX_UNIQUE, 64u * ((batch_tris + 63u) / 64u));
+}
+
+uint64_t units_bound(vr_strategy s, uint64_t T, uint32_t batch_tris) {
+    if (s == VR_STATIC_SORT || s == VR_STATIC_HASH) return (T + batch_tris - 1) / batch_tris;
+    return T;
+}
+
+// Upper bound on dynamic batches: a closed batch holds at least
+// min(N_pmax, ceil((N_u - 2) / 3)) triangles.
+uint64_t dyn_batch_bound(uint64_t T, uint32_t nu, uint32_t tmax) {
+    const uint64_t m = std::max<uint64_t>(1, std::min<uint64_t>(tmax, (nu - 2 + 2) / 3));
+    return T / m + 1;
+}
+
+uint32_t log2u(uint32_t x) {
+    uint32_t b = 0;
+    while ((1u << b) < x) ++b;
+    return b;
+}
+
+struct Resolved {
+    uint32_t nu = 0, nt = 0, max_idx = 0, max_uniq = 0, hash_bits = 0, probes = 4;
+};
+
+vr_status check_args(vr_ctx *c, uint64_t num_indices, const vr_shader_params *sh, vr_strategy strategy,
+                     uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out, Resolved *res) {
+    if (!sh || !out) return fail(c, VR_ERR_ARG, "shader and outputs must not be NULL");
+    if (num_indices % 3 != 0) return fail(c, VR_ERR_ARG, "num_indices %llu is not a multiple of 3",
+                                          (unsigned long long)num_indices);
+    if (num_indices > VR_MAX_INDICES) return fail(c, VR_ERR_ARG, "more than 2^30-1 triangles");
+    if ((int)strategy < 0 || strategy > VR_DYN_BALLOT) return fail(c, VR_ERR_ARG, "unknown strategy %d", (int)strategy);
+    if (batch_tris == 0 || batch_tris > batch_limit(strategy))
+        return fail(c, VR_ERR_ARG, "batch_tris %u outside 1..%u for this strategy", batch_tris, batch_limit(strategy));
+    if (sh->kind > 2) return fail(c, VR_ERR_ARG, "unknown shader kind %u", sh->kind);
+    if (sh->num_lights > VR_MAX_LIGHTS) return fail(c, VR_ERR_ARG, "num_lights %u > 16", sh->num_lights);
+    if (sh->spec_squarings > 8) return fail(c, VR_ERR_ARG, "spec_squarings %u > 8", sh->spec_squarings);
+    if (sh->iterations > 4096) return fail(c, VR_ERR_ARG, "iterations %u > 4096", sh->iterations);
+    vr_opts o{};
+    if (opts) o = *opts;
+    if (o.wg_size != 0 && (o.wg_size % 64 != 0 || o.wg_size > 1024))
+        return fail(c, VR_ERR_ARG, "wg_size %u is not a multiple of 64 up to 1024", o.wg_size);
+    if (o.hash_probes > 64) return fail(c, VR_ERR_ARG, "hash_probes %u > 64", o.hash_probes);
+    Resolved r;
+    if (is_dynamic(strategy)) {
+        r.nu = o.max_unique ? o.max_unique : default_max_unique(batch_tris);
+        if (r.nu < 3 || r.nu > VR_MAX_UNIQUE) return fail(c, VR_ERR_ARG, "max_unique %u outside 3..512", r.nu);
+        r.max_idx = 3 * batch_tris;
+        r.max_uniq = std::min(r.nu, r.max_idx);
+    } else {
+        r.max_idx = 3 * batch_tris;
+        r.max_uniq = 3 * batch_tris;
+    }
+    if (strategy == VR_NAIVE) r.max_idx = r.max_uniq = 3;
+    if (o.hash_slots != 0) {
+        const uint32_t need = is_dynamic(strategy) ? r.nu : 3u * batch_tris;
+        if ((o.hash_slots & (o.hash_slots - 1)) != 0 || o.hash_slots < need || o.hash_slots > 4096)
+            return fail(c, VR_ERR_ARG, "hash_slots %u: need a power of two in %u..4096", o.hash_slots, need);
+    }
+    const uint64_t T = num_indices / 3;
+    if (out->verts && out->verts_cap < 3 * T)
+        return fail(c, VR_ERR_CAPACITY, "verts_cap %llu < 3T", (unsigned long long)out->verts_cap);
+    if ((out->unit_offsets || out->unit_invocations) && out->units_cap < units_bound(strategy, T, batch_tris))
+        return fail(c, VR_ERR_CAPACITY, "units_cap %llu below the bound %llu", (unsigned long long)out->units_cap,
+                    (unsigned long long)units_bound(strategy, T, batch_tris));
+    // launch shape (never changes results)
+    if (strategy != VR_NAIVE && !is_ballot(strategy)) {
+        uint32_t want = o.wg_size ? o.wg_size : std::max<uint32_t>(64, std::min<uint32_t>(256, r.max_uniq));
+        uint32_t nt = 64;
+        while (nt * 2 <= want && nt < 512) nt *= 2;
+        r.nt = nt;
+        const uint32_t slots = o.hash_slots ? o.hash_slots : std::max<uint32_t>(8, 1u << log2u(2 * r.max_uniq));
+        r.hash_bits = log2u(slots);
+        r.probes = o.hash_probes ? o.hash_probes : 4;
+    } else {
+        r.nt = is_ballot(strategy) ? 64 : 256;
+    }
+    if (res) *res = r;
+    return VR_OK;
+}
+
+template <int NT, int MODE, int KIND>
+void launch_dedup(vr_ctx *c, const DrawArgs &A, const vr_shader_params &sh, uint32_t lds, uint64_t units) {
+    auto kern = k_dedup<NT, MODE, KIND>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(units, (uint64_t)c->num_cus * per_cu));
+    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(NT), lds, c->stream, A, sh);
+}
+
+template <int MODE, int KIND>
+void dispatch_nt(vr_ctx *c, uint32_t nt, const DrawArgs &A, const vr_shader_params &sh, uint32_t lds, uint64_t units) {
+    switch (nt) {
+    case 64: launch_dedup<64, MODE, KIND>(c, A, sh, lds, units); break;
+    case 128: launch_dedup<128, MODE, KIND>(c, A, sh, lds, units); break;
+    case 256: launch_dedup<256, MODE, KIND>(c, A, sh, lds, units); break;
+    default: launch_dedup<512, MODE, KIND>(c, A, sh, lds, units); break;
+    }
+}
+
+template <int MODE>
+void dispatch_kind(vr_ctx *c, uint32_t kind, uint32_t nt, const DrawArgs &A, const vr_shader_params &sh, uint32_t lds,
+                   uint64_t units) {
+    if (kind == 0) dispatch_nt<MODE, 0>(c, nt, A, sh, lds, units);
+    else if (kind == 1) dispatch_nt<MODE, 1>(c, nt, A, sh, lds, units);
+    else dispatch_nt<MODE, 2>(c, nt, A, sh, lds, units);
+}
+
+template <int KIND>
+void launch_ballot(vr_ctx *c, const DrawArgs &A, const vr_shader_params &sh, uint32_t lds, uint64_t batches) {
+    auto kern = k_ballot<KIND>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(batches, (uint64_t)c->num_cus * per_cu));
+    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, c->stream, A, sh);
+}
+
+template <int KIND>
+void launch_naive(vr_ctx *c, const DrawArgs &A, const vr_shader_params &sh) {
+    const uint64_t blocks = (3ull * A.T + 255) / 256;
+    hipLaunchKernelGGL(k_naive<KIND>, dim3((uint32_t)blocks), dim3(256), 0, c->stream, A, sh);
+}
+
+__global__ void k_empty_draw(unsigned long long *counters, uint32_t *unit_offsets) {
+    if (threadIdx.x < 4 && counters) counters[threadIdx.x] = 0;
+    if (threadIdx.x == 0 && unit_offsets) unit_offsets[0] = 0;
+}
+
+__global__ void k_plan_empty(uint32_t *plan) {
+    if (threadIdx.x == 0) {
+        plan[0] = 0;
+        plan[1] = 0;
+    }
+}
+
+// Builds the plan of a dynamic draw on the context's stream.
+vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, uint32_t nu, uint32_t tmax,
+                     uint32_t *d_plan) {
+    if (T == 0) {
+        hipLaunchKernelGGL(k_plan_empty, dim3(1), dim3(64), 0, c->stream, d_plan);
+        return VR_OK;
+    }
+    const uint32_t nseg = (T + kPlanSeg - 1) / kPlanSeg;
+    const uint32_t nwords = (T + 63) / 64;
+    const uint32_t nblk = (nwords + 255) / 256;
+    const size_t bytes_bits = 8ull * nwords;
+    const size_t bytes_seg = 4ull * nseg;
+    const size_t total = bytes_bits + 3 * bytes_seg + 4ull * nblk + 256;
+    vr_status st = ensure(c, c->plan_work, total);
+    if (st != VR_OK) return st;
+    unsigned char *base = (unsigned char *)c->plan_work.ptr;
+    PlanArgs P{};
+    P.idx = d_idx;
+    P.V = V;
+    P.T = T;
+    P.cap = nu;
+    P.tmax = tmax;
+    P.nseg = nseg;
+    P.hs_bits = log2u(2 * (nu + 192));
+    P.bits = (unsigned long long *)base;
+    P.spec_last = (uint32_t *)(base + bytes_bits);
+    P.fix_from = P.spec_last + nseg;
+    P.fix_last = P.fix_from + nseg;
+    P.err = &c->d_words->err;
+    uint32_t *block_sums = P.fix_last + nseg;
+    const uint32_t lds = 12u << P.hs_bits;
+    hipLaunchKernelGGL(k_plan_spec, dim3(nseg), dim3(64), lds, c->stream, P);
+    if (nseg > 1) {
+        hipLaunchKernelGGL(k_plan_fix, dim3(nseg - 1), dim3(64), lds, c->stream, P);
+        hipLaunchKernelGGL(k_plan_walk, dim3(1), dim3(64), lds, c->stream, P);
+    }
+    hipLaunchKernelGGL(k_plan_count, dim3(nblk), dim3(256), 0, c->stream, (const unsigned long long *)P.bits, nwords,
+                       block_sums);
+    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, c->stream, block_sums, nblk, d_plan, T);
+    hipLaunchKernelGGL(k_plan_write, dim3(nblk), dim3(256), 0, c->stream, (const unsigned long long *)P.bits, nwords,
+                       (const uint32_t *)block_sums, d_plan);
+    VR_HIP(c, hipGetLastError());
+    return VR_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+vr_status vr_create(vr_ctx **out, int device, void *hip_stream) {
+    if (!out) return fail(nullptr, VR_ERR_ARG, "ctx pointer is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+        return fail(nullptr, VR_ERR_DEVICE, "HIP device %d not available", device);
+    vr_ctx *c = new vr_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    DeviceGuard g(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->num_cus = prop.multiProcessorCount;
+        c->lds_limit = prop.sharedMemPerBlock;
+    }
+    if (hipMalloc((void **)&c->d_words, sizeof(CtxWords)) != hipSuccess ||
+        hipMemset(c->d_words, 0, sizeof(CtxWords)) != hipSuccess) {
+        if (c->d_words) (void)hipFree(c->d_words);
+        delete c;
+        return fail(nullptr, VR_ERR_OOM, "context allocation failed");
+    }
+    *out = c;
+    return VR_OK;
+}
+
+void vr_destroy(vr_ctx *c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (Scratch *s : {&c->status, &c->plan, &c->plan_work})
+        if (s->ptr) (void)hipFree(s->ptr);
+    if (c->d_words) (void)hipFree(c->d_words);
+    delete c;
+}
+
+vr_status vr_set_stream(vr_ctx *c, void *hip_stream) {
+    if (!c) return VR_ERR_ARG;
+    c->stream = (hipStream_t)hip_stream;
+    return VR_OK;
+}
+
+vr_status vr_check_args(uint64_t num_indices, uint32_t num_vertices, const vr_shader_params *shader,
+                        vr_strategy strategy, uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out) {
+    (void)num_vertices;
+    return check_args(nullptr, num_indices, shader, strategy, batch_tris, opts, out, nullptr);
+}
+
+vr_status vr_plan_dynamic(vr_ctx *c, const uint32_t *d_indices, uint64_t num_indices, uint32_t num_vertices,
+                          uint32_t max_unique, uint32_t max_tris, uint32_t *d_plan, uint64_t plan_cap) {
+    if (!c) return VR_ERR_ARG;
+    if (num_indices % 3 != 0 || num_indices > VR_MAX_INDICES)
+        return fail(c, VR_ERR_ARG, "num_indices must be a multiple of 3 below 3*2^30");
+    if (max_unique < 3 || max_unique > VR_MAX_UNIQUE) return fail(c, VR_ERR_ARG, "max_unique outside 3..512");
+    if (max_tris == 0 || max_tris > VR_MAX_BATCH_DYNAMIC) return fail(c, VR_ERR_ARG, "max_tris outside 1..512");
+    const uint64_t T = num_indices / 3;
+    if (!d_plan || plan_cap < T + 2) return fail(c, VR_ERR_CAPACITY, "plan buffer must hold T+2 entries");
+    if (T && !d_indices) return fail(c, VR_ERR_ARG, "indices are NULL");
+    DeviceGuard g(c->device);
+    if (T && num_vertices == 0) {
+        if (!c->host_err) c->host_err = VR_ERR_INDEX_RANGE;
+        return VR_OK;
+    }
+    return build_plan(c, d_indices, (uint32_t)T, num_vertices, max_unique, max_tris, d_plan);
+}
+
+vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_indices, const float *d_vertices,
+                          uint32_t num_vertices, const vr_shader_params *shader, vr_strategy strategy,
+                          uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out) {
+    if (!c) return VR_ERR_ARG;
+    Resolved r;
+    vr_status st = check_args(c, num_indices, shader, strategy, batch_tris, opts, out, &r);
+    if (st != VR_OK) return st;
+    const uint64_t T = num_indices / 3;
+    if (T && (!d_indices || !d_vertices)) return fail(c, VR_ERR_ARG, "indices or vertices are NULL");
+    if (d_vertices && ((uintptr_t)d_vertices & 15)) return fail(c, VR_ERR_ARG, "vertices must be 16-byte aligned");
+    if (out->corners && ((uintptr_t)out->corners & 15)) return fail(c, VR_ERR_ARG, "corners must be 16-byte aligned");
+    if (out->verts && ((uintptr_t)out->verts & 15)) return fail(c, VR_ERR_ARG, "verts must be 16-byte aligned");
+    DeviceGuard g(c->device);
+    if (T == 0) {
+        hipLaunchKernelGGL(k_empty_draw, dim3(1), dim3(64), 0, c->stream, (unsigned long long *)out->counters,
+                           out->unit_offsets);
+        VR_HIP(c, hipGetLastError());
+        return VR_OK;
+    }
+    if (num_vertices == 0) {   // every index is out of range
+        if (!c->host_err) c->host_err = VR_ERR_INDEX_RANGE;
+        return VR_OK;
+    }
+
+    DrawArgs A{};
+    A.idx = d_indices;
+    A.vtx = (const f4 *)d_vertices;
+    A.V = num_vertices;
+    A.T = (uint32_t)T;
+    A.batch_tris = batch_tris;
+    A.corners = (f4 *)out->corners;
+    A.tris = out->tris;
+    A.verts = (f4 *)out->verts;
+    A.local_idx = out->local_idx;
+    A.unit_offsets = out->unit_offsets;
+    A.unit_inv = out->unit_invocations;
+    A.counters = (unsigned long long *)out->counters;
+    A.ticket = &c->d_words->ticket;
+    A.err = &c->d_words->err;
+    A.total_inv = &c->d_words->total_inv;
+    A.hash_bits = r.hash_bits;
+    A.probes = r.probes;
+    A.max_idx = r.max_idx;
+    A.max_uniq = r.max_uniq;
+    A.need_prefix = (out->tris || out->verts || out->unit_offsets || out->unit_invocations) ? 1u : 0u;
+
+    const vr_shader_params &sh = *shader;
+    if (strategy == VR_NAIVE) {
+        if (sh.kind == 0) launch_naive<0>(c, A, sh);
+        else if (sh.kind == 1) launch_naive<1>(c, A, sh);
+        else launch_naive<2>(c, A, sh);
+        VR_HIP(c, hipGetLastError());
+        return VR_OK;
+    }
+
+    uint64_t nb_bound;
+    if (is_dynamic(strategy)) {
+        const uint32_t *plan = opts ? opts->d_plan : nullptr;
+        if (!plan) {
+            st = ensure(c, c->plan, 4ull * (T + 2));
+            if (st != VR_OK) return st;
+            st = build_plan(c, d_indices, (uint32_t)T, num_vertices, r.nu, batch_tris, (uint32_t *)c->plan.ptr);
+            if (st != VR_OK) return st;
+            plan = (const uint32_t *)c->plan.ptr;
+        }
+        A.plan = plan;
+        A.num_batches = 0;
+        nb_bound = dyn_batch_bound(T, r.nu, batch_tris);
+    } else {
+        A.plan = nullptr;
+        A.num_batches = (uint32_t)((T + batch_tris - 1) / batch_tris);
+        nb_bound = A.num_batches;
+    }
+    uint32_t n_status = 0;
+    if (A.need_prefix) {
+        st = ensure(c, c->status, 8ull * nb_bound);
+        if (st != VR_OK) return st;
+        A.status = (unsigned long long *)c->status.ptr;
+        n_status = (uint32_t)nb_bound;
+        A.status_cap = n_status;
+    }
+    const uint32_t reset_threads = std::max<uint32_t>(n_status, 64);
+    hipLaunchKernelGGL(k_reset, dim3((reset_threads + 255) / 256), dim3(256), 0, c->stream, A.ticket, A.counters,
+                       A.status, n_status, A.plan);
+
+    if (is_ballot(strategy)) {
+        const uint32_t lds = 64 * 48 + ((3 * batch_tris + 15) & ~15u);
+        if (sh.kind == 0) launch_ballot<0>(c, A, sh, lds, nb_bound);
+        else if (sh.kind == 1) launch_ballot<1>(c, A, sh, lds, nb_bound);
+        else launch_ballot<2>(c, A, sh, lds, nb_bound);
+    } else {
+        const int mode = (strategy == VR_STATIC_SORT || strategy == VR_DYN_SORT) ? kSort
+                         : (strategy == VR_DYN_PHASH)                             ? kPHash
+                                                                                  : kHash;
+        const uint32_t lds = dedup_lds_layout(mode, r.max_idx, r.max_uniq, r.hash_bits).total;
+        if (lds > c->lds_limit)
+            return fail(c, VR_ERR_ARG, "LDS need %u B exceeds the %zu B limit (lower hash_slots or batch_tris)", lds,
+                        c->lds_limit);
+        if (mode == kSort) dispatch_kind<kSort>(c, sh.kind, r.nt, A, sh, lds, nb_bound);
+        else if (mode == kHash) dispatch_kind<kHash>(c, sh.kind, r.nt, A, sh, lds, nb_bound);
+        else dispatch_kind<kPHash>(c, sh.kind, r.nt, A, sh, lds, nb_bound);
+    }
+    VR_HIP(c, hipGetLastError());
+    return VR_OK;
+}
+
+vr_status vr_sync(vr_ctx *c, uint64_t *h_invocations) {
+    if (!c) return VR_ERR_ARG;
+    DeviceGuard g(c->device);
+    VR_HIP(c, hipStreamSynchronize(c->stream));
+    CtxWords w{};
+    VR_HIP(c, hipMemcpy(&w, c->d_words, sizeof w, hipMemcpyDeviceToHost));
+    VR_HIP(c, hipMemset(c->d_words, 0, sizeof w));
+    if (h_invocations) *h_invocations = w.total_inv;
+    uint32_t e = c->host_err ? c->host_err : w.err;
+    c->host_err = 0;
+    if (e == VR_ERR_INDEX_RANGE) return fail(c, VR_ERR_INDEX_RANGE, "an index is >= num_vertices");
+    if (e != 0) return fail(c, (vr_status)e, "device-side error %u", e);
+    return VR_OK;
+}
+
+const char *vr_last_error(const vr_ctx *c) { return c ? c->error.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

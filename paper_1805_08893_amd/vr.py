@@ -1,0 +1,240 @@
+"""Python binding of libvr.so (the C ABI in include/vr.h).
+
+Argument marshalling only: every step of the geometry stage runs in the
+HIP kernels of libvr.so.  The functions keep the C names; tensors are
+torch CUDA (HIP) tensors whose data pointers are handed to the library.
+If libvr.so is missing this module raises on first use; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvr.so")
+
+VR_OK, VR_ERR_ARG, VR_ERR_INDEX_RANGE, VR_ERR_CAPACITY, VR_ERR_OOM, VR_ERR_DEVICE, VR_ERR_BUSY = range(7)
+(VR_NAIVE, VR_STATIC_BALLOT, VR_STATIC_SORT, VR_STATIC_HASH, VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH,
+ VR_DYN_BALLOT) = range(8)
+STRATEGIES = {"naive": VR_NAIVE, "static_ballot": VR_STATIC_BALLOT, "static_sort": VR_STATIC_SORT,
+              "static_hash": VR_STATIC_HASH, "dyn_sort": VR_DYN_SORT, "dyn_hash": VR_DYN_HASH,
+              "dyn_phash": VR_DYN_PHASH, "dyn_ballot": VR_DYN_BALLOT}
+STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
+DYNAMIC = (VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH, VR_DYN_BALLOT)
+OUT_FLOATS = 12
+
+EXPORTS = ["vr_create", "vr_destroy", "vr_set_stream", "vr_check_args", "vr_plan_dynamic", "vr_process_draw",
+           "vr_sync", "vr_last_error"]
+
+
+class vr_opts(C.Structure):
+    _fields_ = [("max_unique", C.c_uint32), ("wg_size", C.c_uint32), ("hash_slots", C.c_uint32),
+                ("hash_probes", C.c_uint32), ("d_plan", C.c_void_p)]
+
+
+class vr_shader_params(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("num_lights", C.c_uint32), ("iterations", C.c_uint32),
+                ("spec_squarings", C.c_uint32), ("mvp", C.c_float * 16), ("model", C.c_float * 12),
+                ("normal", C.c_float * 9), ("eye", C.c_float * 3), ("ambient", C.c_float * 3),
+                ("kd", C.c_float), ("ks", C.c_float), ("katt", C.c_float), ("coef", C.c_float * 8),
+                ("lights", (C.c_float * 6) * 16)]
+
+
+class vr_outputs(C.Structure):
+    _fields_ = [("corners", C.c_void_p), ("tris", C.c_void_p), ("verts", C.c_void_p),
+                ("verts_cap", C.c_uint64), ("local_idx", C.c_void_p), ("unit_offsets", C.c_void_p),
+                ("unit_invocations", C.c_void_p), ("units_cap", C.c_uint64), ("counters", C.c_void_p)]
+
+
+class VrError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"vr status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libvr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.vr_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, P]
+        L.vr_create.restype = C.c_int
+        L.vr_destroy.argtypes = [P]
+        L.vr_destroy.restype = None
+        L.vr_set_stream.argtypes = [P, P]
+        L.vr_set_stream.restype = C.c_int
+        L.vr_check_args.argtypes = [C.c_uint64, C.c_uint32, C.POINTER(vr_shader_params), C.c_int, C.c_uint32,
+                                    C.POINTER(vr_opts), C.POINTER(vr_outputs)]
+        L.vr_check_args.restype = C.c_int
+        L.vr_plan_dynamic.argtypes = [P, P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, P, C.c_uint64]
+        L.vr_plan_dynamic.restype = C.c_int
+        L.vr_process_draw.argtypes = [P, P, C.c_uint64, P, C.c_uint32, C.POINTER(vr_shader_params), C.c_int,
+                                      C.c_uint32, C.POINTER(vr_opts), C.POINTER(vr_outputs)]
+        L.vr_process_draw.restype = C.c_int
+        L.vr_sync.argtypes = [P, C.POINTER(C.c_uint64)]
+        L.vr_sync.restype = C.c_int
+        L.vr_last_error.argtypes = [P]
+        L.vr_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------- marshalling
+def make_shader(sp) -> vr_shader_params:
+    """From a workloads.ShaderParams (or an object with the same fields)."""
+    s = vr_shader_params()
+    s.kind, s.num_lights, s.iterations, s.spec_squarings = (int(sp.kind), int(sp.num_lights),
+                                                             int(sp.iterations), int(sp.spec_squarings))
+    for name, n in (("mvp", 16), ("model", 12), ("normal", 9), ("eye", 3), ("ambient", 3), ("coef", 8)):
+        arr = np.ascontiguousarray(np.asarray(getattr(sp, name), dtype=np.float32).ravel())
+        assert arr.size == n, name
+        C.memmove(C.addressof(getattr(s, name)), arr.ctypes.data, 4 * n)
+    s.kd, s.ks, s.katt = float(np.float32(sp.kd)), float(np.float32(sp.ks)), float(np.float32(sp.katt))
+    lights = np.ascontiguousarray(np.asarray(sp.lights, dtype=np.float32).reshape(16, 6))
+    C.memmove(C.addressof(s.lights), lights.ctypes.data, 4 * 96)
+    return s
+
+
+def make_opts(max_unique=0, wg_size=0, hash_slots=0, hash_probes=0, plan=None) -> vr_opts:
+    return vr_opts(max_unique, wg_size, hash_slots, hash_probes, None if plan is None else plan.data_ptr())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# ---------------------------------------------------------------- C names
+def vr_create(device=0, stream=None):
+    h = C.c_void_p()
+    st = lib().vr_create(C.byref(h), int(device), _stream_handle(stream))
+    if st != VR_OK:
+        raise VrError(st, lib().vr_last_error(None).decode())
+    return h
+
+
+def vr_destroy(ctx):
+    lib().vr_destroy(ctx)
+
+
+def vr_set_stream(ctx, stream):
+    return lib().vr_set_stream(ctx, _stream_handle(stream))
+
+
+def vr_last_error(ctx=None):
+    return lib().vr_last_error(ctx).decode()
+
+
+def vr_check_args(num_indices, num_vertices, shader, strategy, batch_tris, opts=None, outputs=None):
+    sh = shader if isinstance(shader, vr_shader_params) else make_shader(shader)
+    out = outputs if outputs is not None else vr_outputs()
+    return lib().vr_check_args(num_indices, num_vertices, C.byref(sh), strategy, batch_tris,
+                               C.byref(opts) if opts is not None else None, C.byref(out))
+
+
+def vr_plan_dynamic(ctx, indices, num_vertices, max_unique, max_tris, plan):
+    return lib().vr_plan_dynamic(ctx, _ptr(indices), indices.numel(), num_vertices, max_unique, max_tris,
+                                 _ptr(plan), plan.numel())
+
+
+def vr_process_draw(ctx, indices, vertices, shader, strategy, batch_tris, opts=None, outputs=None):
+    sh = shader if isinstance(shader, vr_shader_params) else make_shader(shader)
+    out = outputs if outputs is not None else vr_outputs()
+    V = vertices.shape[0] if vertices.dim() == 2 else vertices.numel() // 8
+    return lib().vr_process_draw(ctx, _ptr(indices), indices.numel(), _ptr(vertices), V, C.byref(sh),
+                                 strategy, batch_tris, C.byref(opts) if opts is not None else None,
+                                 C.byref(out))
+
+
+def vr_sync(ctx):
+    inv = C.c_uint64(0)
+    st = lib().vr_sync(ctx, C.byref(inv))
+    return st, int(inv.value)
+
+
+# ---------------------------------------------------------------- convenience
+class GeometryStage:
+    """A context plus output allocation with torch (device memory only)."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.ctx = vr_create(device, stream if stream is not None else torch.cuda.current_stream(device))
+
+    def close(self):
+        if self.ctx is not None:
+            vr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st):
+        if st != VR_OK:
+            raise VrError(st, vr_last_error(self.ctx))
+
+    def alloc_outputs(self, num_tris, strategy, batch_tris, corners=True, tris=False, verts=False,
+                      local_idx=False, units=False):
+        torch = self.torch
+        n = 3 * num_tris
+        res = {"counters": torch.zeros(4, dtype=torch.int64, device=self.device)}
+        if corners:
+            res["corners"] = torch.empty((n, OUT_FLOATS), dtype=torch.float32, device=self.device)
+        if tris:
+            res["tris"] = torch.empty(n, dtype=torch.int32, device=self.device)
+        if verts:
+            res["verts"] = torch.empty((max(n, 1), OUT_FLOATS), dtype=torch.float32, device=self.device)
+        if local_idx:
+            res["local_idx"] = torch.empty(n, dtype=torch.int16, device=self.device)
+        if units:
+            ucap = units_bound(strategy, num_tris, batch_tris)
+            res["unit_offsets"] = torch.empty(ucap + 1, dtype=torch.int32, device=self.device)
+            res["unit_invocations"] = torch.empty(max(ucap, 1), dtype=torch.int32, device=self.device)
+        return res
+
+    @staticmethod
+    def describe(res):
+        def p(k):
+            t = res.get(k)
+            return None if t is None else t.data_ptr()
+        ucap = res["unit_invocations"].numel() if res.get("unit_invocations") is not None else 0
+        vcap = res["verts"].shape[0] if res.get("verts") is not None else 0
+        return vr_outputs(p("corners"), p("tris"), p("verts"), vcap, p("local_idx"), p("unit_offsets"),
+                          p("unit_invocations"), ucap, p("counters"))
+
+    def draw(self, indices, vertices, shader, strategy, batch_tris, opts=None, res=None, **want):
+        if res is None:
+            res = self.alloc_outputs(indices.numel() // 3, strategy, batch_tris, **want)
+        o = opts if (opts is None or isinstance(opts, vr_opts)) else make_opts(**opts)
+        st = vr_process_draw(self.ctx, indices, vertices, shader, strategy, batch_tris, o, self.describe(res))
+        self.check(st)
+        return res
+
+    def sync(self):
+        st, inv = vr_sync(self.ctx)
+        return st, inv
+
+
+def units_bound(strategy, num_tris, batch_tris):
+    if strategy in (VR_STATIC_SORT, VR_STATIC_HASH):
+        return (num_tris + batch_tris - 1) // batch_tris
+    return num_tris
