@@ -49,6 +49,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-passes", type=int, default=1)
     ap.add_argument("--level", type=int, default=8, help="icosphere subdivision level")
+    ap.add_argument("--only", default=None, help="run only this strategy in each step (profiling)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="time a plain device-to-device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the geometry stage has no cross-GPU path "
@@ -60,6 +63,20 @@ def main():
     from paper_1805_08893_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"copy_bytes": args.copy_probe, "ms": dt * 1e3,
+                          "read_plus_write_GBps": 2 * args.copy_probe / dt / 1e9}), flush=True)
+        return
     mesh, sp = W.icosphere8_hilbert_phong8(level=args.level)
     T, V = mesh.num_tris, mesh.num_verts
     U = int(len(np.unique(mesh.indices)))
@@ -73,6 +90,9 @@ def main():
                   ("dyn_sort", vr.VR_DYN_SORT, NP, dict(max_unique=NU, plan=plan)),
                   ("dyn_hash", vr.VR_DYN_HASH, NP, dict(max_unique=NU, plan=plan)),
                   ("dyn_phash", vr.VR_DYN_PHASH, NP, dict(max_unique=NU, plan=plan))]
+    if args.only:
+        strategies = [s for s in strategies if s[0] == args.only]
+        assert strategies, f"unknown strategy {args.only}"
     res = {name: stage.alloc_outputs(T, s, bt, corners=True) for name, s, bt, _ in strategies}
     opts = {name: vr.make_opts(**o) for name, _, _, o in strategies}
     shader = vr.make_shader(sp)
@@ -124,7 +144,7 @@ def main():
         p.update({"tri_per_s": T / (p["ms_mean"] * 1e-3), "invocations": inv, "shading_rate": inv / U,
                   "reuse": 1.0 - inv / (3.0 * T), "speedup_vs_naive": None})
     for name, *_ in strategies:
-        per[name]["speedup_vs_naive"] = per["naive"]["ms_mean"] / per[name]["ms_mean"]
+        per[name]["speedup_vs_naive"] = (per["naive"]["ms_mean"] / per[name]["ms_mean"]) if "naive" in per else None
 
     # dominant kernel: the slowest draw of the step
     dom = max((s[0] for s in strategies), key=lambda n: per[n]["ms_mean"])

@@ -172,9 +172,11 @@ __device__ __forceinline__ void lookback_publish(unsigned long long *status, uin
 }
 
 // Returns the exclusive prefix of unit b (packed), called by one thread
-// after lookback_publish.  Waits on predecessors, which hold lower tickets
-// and therefore already run; a bounded spin turns a lost update into an
-// error instead of a hang.
+// after lookback_publish.  Unit b is workgroup b.  Workgroups are dispatched
+// in index order within each XCD (the grid is dealt round-robin over the
+// XCDs), so when b runs, the lowest unfinished unit has been dispatched or
+// its XCD holds only lower, finishing units: every wait ends.  A bounded
+// spin still turns a lost update into an error instead of a hang.
 __device__ __forceinline__ uint64_t lookback_resolve(unsigned long long *status, uint32_t b, uint64_t agg,
                                                      uint32_t *err) {
     if (b == 0) return 0;

@@ -25,8 +25,8 @@ struct DrawArgs {
     uint32_t *unit_offsets;     // [units + 1]
     uint32_t *unit_inv;         // [units]
     unsigned long long *counters;   // [4]
-    uint32_t *ticket;           // work counter, zeroed per launch
-    unsigned long long *status; // look-back words, zeroed per launch
+    unsigned long long *agg;    // per batch: (units << 32) | invocations
+    unsigned long long *status; // look-back words, zero at launch (cleared by k_finish)
     uint32_t *err;              // first device-side error
     unsigned long long *total_inv;  // invocations since the last vr_sync
     uint32_t hash_bits;         // log2 of the LDS hash-table size
@@ -118,15 +118,36 @@ __device__ __forceinline__ void write_unit(const DrawArgs &A, uint32_t t0, uint3
 }
 
 // ---------------------------------------------------------------------------
-// Per-launch reset of the work counter, counters and look-back words.
+// End of a batched draw: one workgroup sums the per-batch aggregates into the
+// counters (no same-address atomics on the hot path) and clears the
+// look-back words for the next launch.
 // ---------------------------------------------------------------------------
-__global__ void k_reset(uint32_t *ticket, unsigned long long *counters, unsigned long long *status,
-                        uint32_t n_status, const uint32_t *plan) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t n = plan ? min(n_status, plan[0]) : n_status;
-    if (i < n) status[i] = 0;
-    if (i == 0) *ticket = 0;
-    if (counters && i < 4) counters[i] = 0;
+__global__ __launch_bounds__(1024) void k_finish(const uint32_t *plan, uint32_t num_batches, uint32_t status_cap,
+                                                 const unsigned long long *agg, unsigned long long *status,
+                                                 unsigned long long *counters, unsigned long long *total_inv) {
+    __shared__ unsigned long long part[16];
+    uint32_t nb = plan ? plan[0] : num_batches;
+    if (nb > status_cap) nb = status_cap;
+    unsigned long long sum = 0;
+    for (uint32_t i = threadIdx.x; i < nb; i += 1024) {
+        sum += agg[i];
+        if (status) status[i] = 0;
+    }
+    for (int d = 32; d > 0; d >>= 1) sum += __shfl_down(sum, d, kWave);
+    if (lane_id() == 0) part[threadIdx.x / kWave] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 16; ++w) t += part[w];
+        const unsigned long long inv = t & 0xFFFFFFFFull, units = t >> 32;
+        if (counters) {
+            counters[0] = inv;
+            counters[1] = units;
+            counters[2] = 0;
+            counters[3] = 0;
+        }
+        *total_inv += inv;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -165,6 +186,8 @@ __global__ __launch_bounds__(256) void k_naive(DrawArgs A, vr_shader_params sh) 
         if (A.counters) {
             A.counters[0] = n;
             A.counters[1] = A.T;
+            A.counters[2] = 0;
+            A.counters[3] = 0;
         }
         atomicAdd(A.total_inv, (unsigned long long)n);
     }
@@ -248,8 +271,8 @@ __device__ __forceinline__ uint32_t rank_flagged(uint32_t n, uint32_t *s_tmp, Fl
 
 // ---------------------------------------------------------------------------
 // Batched deduplication + shading + assembly (Algorithms 2 and 3, and the
-// parallel-hashing variant).  Persistent workgroups take units in ticket
-// order; a unit of n corners is deduplicated in LDS into inv unique
+// parallel-hashing variant).  Workgroup u owns unit u (no atomics to pick
+// work); a unit of n corners is deduplicated in LDS into inv unique
 // vertices with canonical local ids:
 //   sort  - ascending rank among distinct indices (Algorithm 2),
 //   hash  - first-occurrence order (Algorithm 3, ids made independent of
@@ -266,16 +289,13 @@ __global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh) {
     uint32_t *s_uniq = (uint32_t *)(smem + L.uniq);
     f4 *s_sv = (f4 *)(smem + L.sv);
     uint32_t *s_tmp = (uint32_t *)(smem + L.tmp);
-    __shared__ uint32_t s_unit, s_vbase;
+    __shared__ uint32_t s_vbase;
 
     const uint32_t tid = threadIdx.x, lane = lane_id();
     const uint32_t nb = launch_units(A, batch_count(A));
-    unsigned long long my_inv = 0;
-    for (;;) {
-        if (tid == 0) s_unit = atomicAdd(A.ticket, 1u);
-        __syncthreads();
-        const uint32_t u = s_unit;
-        if (u >= nb) break;
+    const uint32_t u = blockIdx.x;
+    if (u >= nb) return;
+    {
         uint32_t t0, t1;
         batch_range(A, u, t0, t1);
         uint32_t n = 3 * (t1 - t0);
@@ -425,14 +445,8 @@ __global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh) {
         }
         __syncthreads();
         if (fits && (inv > 0 || n == 0)) write_unit<NT>(A, t0, t1 - t0, s_local, s_sv, inv, s_vbase, u);
-        if (tid == 0) my_inv += inv;
-        __syncthreads();
+        if (tid == 0) A.agg[u] = (1ull << 32) | inv;
     }
-    if (tid == 0 && my_inv) {
-        atomicAdd(A.total_inv, my_inv);
-        if (A.counters) atomicAdd(&A.counters[0], my_inv);
-    }
-    if (blockIdx.x == 0 && tid == 0 && A.counters) atomicAdd(&A.counters[1], (unsigned long long)nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -508,12 +522,9 @@ __global__ __launch_bounds__(64) void k_ballot(DrawArgs A, vr_shader_params sh) 
     uint8_t *s_map = smem + 64 * 48;          // local id per corner of a round
     const uint32_t lane = lane_id();
     const uint32_t nb = launch_units(A, batch_count(A));
-    unsigned long long my_inv = 0, my_units = 0;
-    for (;;) {
-        uint32_t b = 0;
-        if (lane == 0) b = atomicAdd(A.ticket, 1u);
-        b = __builtin_amdgcn_readfirstlane(b);
-        if (b >= nb) break;
+    const uint32_t b = blockIdx.x;
+    if (b >= nb) return;
+    {
         uint32_t t0, t1;
         batch_range(A, b, t0, t1);
         if (t1 < t0 || 3 * (t1 - t0) > A.max_idx) {   // only with a plan built for other limits
@@ -539,7 +550,7 @@ __global__ __launch_bounds__(64) void k_ballot(DrawArgs A, vr_shader_params sh) 
             vbase = __builtin_amdgcn_readfirstlane((uint32_t)ex);
             ubase = __builtin_amdgcn_readfirstlane((uint32_t)((ex >> 32) & 0x3FFFFFFFu));
         }
-        uint32_t r = 0;
+        uint32_t r = 0, inv = 0;
         for (uint32_t cur = t0; cur < t1; ++r) {
             const uint32_t end = ballot_round(A, cur, t1, s_map, st);
             if (lane < st.fill) shade_to_lds<KIND>(A, sh, st.my_id, s_sv + 3 * lane);
@@ -547,18 +558,11 @@ __global__ __launch_bounds__(64) void k_ballot(DrawArgs A, vr_shader_params sh) 
             write_unit<64>(A, cur, end - cur, s_map, s_sv, st.fill, vbase, ubase + r);
             __syncthreads();
             vbase += st.fill;
-            my_inv += st.fill;
+            inv += st.fill;
             cur = end;
         }
-        my_units += r;
         if (A.unit_offsets && b + 1 == nb && lane == 0) A.unit_offsets[ubase + r] = A.T;
-    }
-    if (lane == 0) {
-        if (my_inv) atomicAdd(A.total_inv, my_inv);
-        if (A.counters && my_inv) {
-            atomicAdd(&A.counters[0], my_inv);
-            atomicAdd(&A.counters[1], my_units);
-        }
+        if (lane == 0) A.agg[b] = ((unsigned long long)r << 32) | inv;
     }
 }
 

@@ -19,11 +19,11 @@ namespace {
 
 thread_local std::string g_create_error;
 
-// Device words owned by a context: error code, work ticket, and the
-// invocation total since the last vr_sync.
+// Device words owned by a context: error code and the invocation total
+// since the last vr_sync.
 struct CtxWords {
     uint32_t err;
-    uint32_t ticket;
+    uint32_t pad;
     unsigned long long total_inv;
 };
 
@@ -41,7 +41,7 @@ struct vr_ctx {
     size_t lds_limit = 65536;
     std::string error;
     CtxWords *d_words = nullptr;
-    Scratch status, plan, plan_work;
+    Scratch status, agg, plan, plan_work;
     uint32_t host_err = 0;   // data error found on the host, reported by vr_sync
 };
 
@@ -80,7 +80,7 @@ vr_status fail(vr_ctx *c, vr_status s, const char *fmt, ...) {
 
 // Grow-only scratch.  The stream is drained before a buffer is replaced
 // because enqueued kernels may still use the old one.
-vr_status ensure(vr_ctx *c, Scratch &s, size_t bytes) {
+vr_status ensure(vr_ctx *c, Scratch &s, size_t bytes, bool zero = false) {
     if (bytes <= s.bytes) return VR_OK;
     bytes = std::max<size_t>(bytes, 2 * s.bytes);
     if (s.ptr) {
@@ -94,6 +94,7 @@ vr_status ensure(vr_ctx *c, Scratch &s, size_t bytes) {
         return fail(c, VR_ERR_OOM, "scratch allocation of %zu bytes failed", bytes);
     }
     s.bytes = bytes;
+    if (zero) VR_HIP(c, hipMemsetAsync(s.ptr, 0, bytes, c->stream));
     return VR_OK;
 }
 
@@ -194,11 +195,7 @@ vr_status check_args(vr_ctx *c, uint64_t num_indices, const vr_shader_params *sh
 
 template <int NT, int MODE, int KIND>
 void launch_dedup(vr_ctx *c, const DrawArgs &A, const vr_shader_params &sh, uint32_t lds, uint64_t units) {
-    auto kern = k_dedup<NT, MODE, KIND>;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, lds) != hipSuccess || per_cu < 1) per_cu = 1;
-    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(units, (uint64_t)c->num_cus * per_cu));
-    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(NT), lds, c->stream, A, sh);
+    hipLaunchKernelGGL((k_dedup<NT, MODE, KIND>), dim3((uint32_t)units), dim3(NT), lds, c->stream, A, sh);
 }
 
 template <int MODE, int KIND>
@@ -221,11 +218,7 @@ void dispatch_kind(vr_ctx *c, uint32_t kind, uint32_t nt, const DrawArgs &A, con
 
 template <int KIND>
 void launch_ballot(vr_ctx *c, const DrawArgs &A, const vr_shader_params &sh, uint32_t lds, uint64_t batches) {
-    auto kern = k_ballot<KIND>;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess || per_cu < 1) per_cu = 1;
-    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(batches, (uint64_t)c->num_cus * per_cu));
-    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, c->stream, A, sh);
+    hipLaunchKernelGGL(k_ballot<KIND>, dim3((uint32_t)batches), dim3(64), lds, c->stream, A, sh);
 }
 
 template <int KIND>
@@ -327,7 +320,7 @@ void vr_destroy(vr_ctx *c) {
     if (!c) return;
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (Scratch *s : {&c->status, &c->plan, &c->plan_work})
+    for (Scratch *s : {&c->status, &c->agg, &c->plan, &c->plan_work})
         if (s->ptr) (void)hipFree(s->ptr);
     if (c->d_words) (void)hipFree(c->d_words);
     delete c;
@@ -400,7 +393,6 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
     A.unit_offsets = out->unit_offsets;
     A.unit_inv = out->unit_invocations;
     A.counters = (unsigned long long *)out->counters;
-    A.ticket = &c->d_words->ticket;
     A.err = &c->d_words->err;
     A.total_inv = &c->d_words->total_inv;
     A.hash_bits = r.hash_bits;
@@ -436,18 +428,20 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
         A.num_batches = (uint32_t)((T + batch_tris - 1) / batch_tris);
         nb_bound = A.num_batches;
     }
-    uint32_t n_status = 0;
+    // one workgroup per batch; a dynamic launch covers the batch bound and
+    // workgroups past the plan's count return at once
+    st = ensure(c, c->agg, 8ull * nb_bound);
+    if (st != VR_OK) return st;
+    A.agg = (unsigned long long *)c->agg.ptr;
     if (A.need_prefix) {
-        st = ensure(c, c->status, 8ull * nb_bound);
+        st = ensure(c, c->status, 8ull * nb_bound, /*zero=*/true);
         if (st != VR_OK) return st;
         A.status = (unsigned long long *)c->status.ptr;
-        n_status = (uint32_t)nb_bound;
-        A.status_cap = n_status;
+        A.status_cap = (uint32_t)nb_bound;
+    } else {
+        A.status = nullptr;
+        A.status_cap = (uint32_t)nb_bound;
     }
-    const uint32_t reset_threads = std::max<uint32_t>(n_status, 64);
-    hipLaunchKernelGGL(k_reset, dim3((reset_threads + 255) / 256), dim3(256), 0, c->stream, A.ticket, A.counters,
-                       A.status, n_status, A.plan);
-
     if (is_ballot(strategy)) {
         const uint32_t lds = 64 * 48 + ((3 * batch_tris + 15) & ~15u);
         if (sh.kind == 0) launch_ballot<0>(c, A, sh, lds, nb_bound);
@@ -465,6 +459,8 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
         else if (mode == kHash) dispatch_kind<kHash>(c, sh.kind, r.nt, A, sh, lds, nb_bound);
         else dispatch_kind<kPHash>(c, sh.kind, r.nt, A, sh, lds, nb_bound);
     }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, c->stream, A.plan, A.num_batches, A.status_cap,
+                       (const unsigned long long *)A.agg, A.status, A.counters, A.total_inv);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
 }
