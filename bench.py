@@ -64,18 +64,23 @@ def main():
 
     torch.cuda.set_device(0)
     if args.copy_probe:
-        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(args.warmup):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        print(json.dumps({"copy_bytes": args.copy_probe, "ms": dt * 1e3,
-                          "read_plus_write_GBps": 2 * args.copy_probe / dt / 1e9}), flush=True)
+        out = {"copy_bytes": args.copy_probe}
+        for name, fn in (("copy", lambda: dst.copy_(src)), ("fill", lambda: dst.fill_(2.0))):
+            for _ in range(args.warmup):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            moved = (2 if name == "copy" else 1) * args.copy_probe
+            out[name] = {"ms": ms, "GBps": moved / (ms * 1e-3) / 1e9}
+        print(json.dumps(out), flush=True)
         return
     mesh, sp = W.icosphere8_hilbert_phong8(level=args.level)
     T, V = mesh.num_tris, mesh.num_verts

@@ -113,13 +113,17 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Inclusive scan over the 64 lanes with DPP: Hillis-Steele steps of 1, 2, 4
+// and 8 lanes inside each 16-lane row, then row 0's and row 2's totals are
+// broadcast into rows 1 and 3 (row_bcast:15) and the total of rows 0-1 into
+// rows 2 and 3 (row_bcast:31).  Lanes whose source is out of range add 0.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t u = __shfl_up(v, d, kWave);
-        if (lane >= (uint32_t)d) v += u;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
     return v;
 }
 
@@ -131,7 +135,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
     const uint32_t tid = threadIdx.x, w = tid / kWave, lane = lane_id();
     uint32_t incl = wave_incl_scan(v);
     if (NW == 1) {
-        total = __shfl(incl, kWave - 1, kWave);
+        total = __builtin_amdgcn_readlane(incl, kWave - 1);
         return incl - v;
     }
     if (lane == kWave - 1) tmp[w] = incl;

@@ -248,11 +248,9 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     }
     const uint32_t nseg = (T + kPlanSeg - 1) / kPlanSeg;
     const uint32_t nwords = (T + 63) / 64;
-    const uint32_t nblk = (nwords + 255) / 256;
     const size_t bytes_bits = 8ull * nwords;
     const size_t bytes_seg = 4ull * nseg;
-    const size_t total = bytes_bits + 3 * bytes_seg + 4ull * nblk + 256;
-    vr_status st = ensure(c, c->plan_work, total);
+    vr_status st = ensure(c, c->plan_work, bytes_bits + 3 * bytes_seg + 256);
     if (st != VR_OK) return st;
     unsigned char *base = (unsigned char *)c->plan_work.ptr;
     PlanArgs P{};
@@ -262,24 +260,18 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     P.cap = nu;
     P.tmax = tmax;
     P.nseg = nseg;
+    P.nwords = nwords;
     P.hs_bits = log2u(2 * (nu + 192));
     P.bits = (unsigned long long *)base;
     P.spec_last = (uint32_t *)(base + bytes_bits);
     P.fix_from = P.spec_last + nseg;
     P.fix_last = P.fix_from + nseg;
+    P.plan = d_plan;
     P.err = &c->d_words->err;
-    uint32_t *block_sums = P.fix_last + nseg;
-    const uint32_t lds = 12u << P.hs_bits;
+    const uint32_t lds = plan_chain_lds(P.hs_bits);
     hipLaunchKernelGGL(k_plan_spec, dim3(nseg), dim3(64), lds, c->stream, P);
-    if (nseg > 1) {
-        hipLaunchKernelGGL(k_plan_fix, dim3(nseg - 1), dim3(64), lds, c->stream, P);
-        hipLaunchKernelGGL(k_plan_walk, dim3(1), dim3(64), lds, c->stream, P);
-    }
-    hipLaunchKernelGGL(k_plan_count, dim3(nblk), dim3(256), 0, c->stream, (const unsigned long long *)P.bits, nwords,
-                       block_sums);
-    hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(1024), 0, c->stream, block_sums, nblk, d_plan, T);
-    hipLaunchKernelGGL(k_plan_write, dim3(nblk), dim3(256), 0, c->stream, (const unsigned long long *)P.bits, nwords,
-                       (const uint32_t *)block_sums, d_plan);
+    if (nseg > 1) hipLaunchKernelGGL(k_plan_fix, dim3(nseg - 1), dim3(64), lds, c->stream, P);
+    hipLaunchKernelGGL(k_plan_walk_pack, dim3(1), dim3(1024), lds, c->stream, P);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
 }
