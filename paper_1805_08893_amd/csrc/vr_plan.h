@@ -1,365 +1,397 @@
 // Dynamic batching on the device (Section 3.4, "Dynamic batching").
 //
-// The cut rule is a sequential greedy chain: starting at a batch start,
-// whole triangles are added while the batch has at most N_u distinct indices
-// and at most N_pmax triangles; the first triangle that would break a limit
-// starts the next batch.  The chain is made parallel by speculation:
-//   spec   one wavefront per segment of kPlanSeg triangles runs the chain
-//          from the segment's first triangle, marking cuts in the segment's
-//          bitmap words and recording the batch still open at its end;
-//   fix    one wavefront per segment s >= 1 continues the chain of segment
-//          s-1 from that open batch into s until it produces a cut that s
-//          already holds: from there on both chains coincide (the greedy
-//          rule is deterministic from any cut), so only the bits before the
-//          meeting point change;
-//   walk   one wavefront visits the segments whose fix started from a batch
-//          start that changed meanwhile and redoes them in order; then the
-//          whole workgroup compacts the bitmap into [B, start_0.., T].
-// The result equals the sequential chain exactly for any segment length.
-// Indices and cut bits live in LDS while a chain runs: global memory sees one
-// coalesced index load and one bitmap write-back per segment.
+// The cut rule is a sequential greedy chain: a batch that starts at triangle
+// c takes whole triangles while it has at most N_u distinct indices and at
+// most N_pmax triangles; the first triangle that would break a limit starts
+// the next batch.  Write next(c) for the end of the batch that starts at c;
+// the plan is the chain 0, next(0), next(next(0)), ...  It is computed
+// exactly, in parallel, in three steps:
+//
+//  1. next(c) for every c (k_plan_next).  A workgroup stages the indices of
+//     256 starts plus N_pmax triangles in LDS, finds every corner's previous
+//     occurrence in that window (hash slots, bucketed by a counting sort),
+//     and one lane per start adds up the corners whose previous occurrence
+//     lies before the start until the budget would be exceeded.
+//  2. Transfer tables (k_plan_table, k_plan_compose).  The triangles are cut
+//     into segments of L >= N_pmax triangles.  The chain's state at a
+//     segment boundary is its first position at or after the boundary, which
+//     lies within N_pmax triangles of it.  For every possible entry offset a
+//     table gives the exit offset at the segment's end (pointer jumping over
+//     next() in LDS); tables of 32 consecutive ranges are composed into one,
+//     level by level, until at most 32 remain.
+//  3. Resolution (k_plan_top, k_plan_resolve, k_plan_emit, k_plan_pack).  The
+//     top tables are applied in order from entry 0, entries are pushed down
+//     the levels, every segment walks next() from its entry to list its batch
+//     starts, and the lists are packed into [B, start_0, .., start_{B-1}, T].
+// Every step does bounded parallel work whatever the batch structure; the
+// result equals the sequential chain exactly.
 #pragma once
 
 #include "vr_device.h"
 
 namespace vr {
 
-constexpr uint32_t kPlanSeg = 512;            // triangles per segment (multiple of 64)
-constexpr uint32_t kSegWords = kPlanSeg / 64; // bitmap words per segment
-static_assert(kPlanSeg >= VR_MAX_BATCH_DYNAMIC, "a batch must not outgrow one segment");
+constexpr uint32_t kNextBlock = 256;                         // starts per workgroup
+constexpr uint32_t kNextTris = kNextBlock + VR_MAX_BATCH_DYNAMIC;
+constexpr uint32_t kNextSlots = 4096;                        // LDS hash slots (>= 3 * kNextTris)
+constexpr uint32_t kFanIn = 32;                              // tables composed per group
+constexpr uint16_t kEnd = 0xFFFF;                            // table value: the chain has ended
+constexpr uint32_t kNone = 0xFFFF;                           // no previous occurrence
+static_assert(kNextSlots >= 3 * kNextTris, "hash table must hold every staged corner");
 
 struct PlanArgs {
     const uint32_t *idx;
     uint32_t V, T;
-    uint32_t cap, tmax;                   // N_u, N_pmax
-    uint32_t nseg, nwords;
-    uint32_t hs_bits;                     // per-wave set size: 2^hs_bits slots
-    unsigned long long *bits;             // cut bitmap, nwords words (kSegWords per segment)
-    uint32_t *spec_last;                  // [nseg] batch open at the segment end (speculative)
-    uint32_t *fix_from;                   // [nseg] batch start the fix of s started from
-    uint32_t *fix_last;                   // [nseg] batch open at the end of s after its fix
-    uint32_t *plan;                       // output [B, starts.., T]
+    uint32_t cap, tmax;        // N_u, N_pmax
+    uint32_t seg_len, nseg;    // L and the number of segments
+    uint32_t *next;            // [T]
     uint32_t *err;
 };
 
-// LDS of one chain-running wavefront.
-struct ChainLds {
-    uint32_t *tab;             // set of the open batch's indices (kEmpty = free)
-    uint32_t *pos;             // first corner position of each key in the open batch
-    uint32_t *cache;           // indices of triangles [c0, c0 + cn)
-    unsigned long long *sbits; // the segment's kSegWords bitmap words
-    uint32_t hs_bits, mask;
-    uint32_t c0, cn;
-};
+__device__ __forceinline__ uint32_t seg_lo(const PlanArgs &P, uint32_t s) { return s * P.seg_len; }
+__device__ __forceinline__ uint32_t seg_hi(const PlanArgs &P, uint32_t s) { return min(P.T, (s + 1) * P.seg_len); }
 
-__host__ __device__ inline uint32_t plan_chain_lds(uint32_t hs_bits) {
-    return (8u << hs_bits) + 3u * 4u * 2u * kPlanSeg + 8u * kSegWords;
-}
+// ---------------------------------------------------------------------------
+// 1. next(c) for every start c
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
+    // LDS regions are reused once their first contents are dead:
+    //   s_a: indices (insert) -> corner positions grouped by slot + start counts
+    //   s_tab: keys (insert) -> bucket starts | bucket ends (2 x uint16)
+    //   s_cnt: slot counts -> 3 x 16-bit previous occurrence per triangle
+    __shared__ uint32_t s_a[3 * kNextTris];
+    __shared__ uint32_t s_tab[kNextSlots];
+    __shared__ unsigned long long s_cntprev[kNextSlots / 4];
+    __shared__ uint32_t s_tmp[4];
+    static_assert(kNextSlots / 4 >= kNextTris + 4, "previous-occurrence table fits the count array");
+    uint16_t *s_cnt = (uint16_t *)s_cntprev;
+    unsigned long long *s_prev = s_cntprev;
+    static_assert((3 * kNextTris) % 256 == 0, "corners split evenly over the threads");
+    uint32_t *s_key = s_a;
+    uint16_t *s_arr = (uint16_t *)s_a;                       // 3 * kNextTris entries
+    int *s_diff = (int *)(s_a + (3 * kNextTris + 1) / 2);    // kNextBlock + 1 entries
+    uint16_t *s_start = (uint16_t *)s_tab, *s_end = s_start + kNextSlots;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t c0 = blockIdx.x * kNextBlock;
+    const uint32_t r1 = min(P.T, c0 + kNextBlock + P.tmax);
+    const uint32_t n = 3 * (r1 - c0);
 
-__device__ __forceinline__ ChainLds chain_lds(unsigned char *smem, uint32_t hs_bits) {
-    ChainLds S;
-    S.tab = (uint32_t *)smem;
-    S.pos = (uint32_t *)(smem + (4u << hs_bits));
-    S.cache = (uint32_t *)(smem + (8u << hs_bits));
-    S.sbits = (unsigned long long *)(smem + (8u << hs_bits) + 3u * 4u * 2u * kPlanSeg);
-    S.hs_bits = hs_bits;
-    S.mask = (1u << hs_bits) - 1;
-    S.c0 = S.cn = 0;
-    return S;
-}
-
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Empties the set (a new batch opens).
-__device__ __forceinline__ void chain_clear_set(ChainLds &S) {
-    for (uint32_t i = lane_id(); i <= S.mask; i += kWave) {
-        S.tab[i] = kEmpty;
-        S.pos[i] = kEmpty;
-    }
-    wave_sync_lds();
-}
-
-// Stages the indices of triangles [t0, t1) (at most 2 * kPlanSeg) in LDS,
-// with the range check applied once here.
-__device__ __forceinline__ void chain_load(const PlanArgs &P, ChainLds &S, uint32_t t0, uint32_t t1) {
-    if (t1 - t0 > 2 * kPlanSeg) {   // cannot happen while N_pmax <= kPlanSeg
-        raise_error(P.err, VR_ERR_DEVICE);
-        t1 = t0 + 2 * kPlanSeg;
-    }
-    const uint32_t n = 3 * (t1 - t0);
-    const uint32_t *src = P.idx + 3ull * t0;
-    for (uint32_t i = lane_id(); i < n; i += kWave) {
-        uint32_t v = src[i];
+    for (uint32_t i = tid; i < n; i += 256) {
+        uint32_t v = P.idx[3ull * c0 + i];
         if (v >= P.V) {
             raise_error(P.err, VR_ERR_INDEX_RANGE);
             v = 0;
         }
-        S.cache[i] = v;
+        s_key[i] = v;
     }
-    S.c0 = t0;
-    S.cn = t1 - t0;
-}
-
-// Finds or inserts `key` (linear probing; the set never fills: it holds at
-// most N_u + 192 keys in 2 * (N_u + 192) or more slots).
-__device__ __forceinline__ uint32_t chain_slot(ChainLds &S, uint32_t key) {
-    uint32_t p = hash_slot(key, S.hs_bits);
-    for (;;) {
-        const uint32_t prev = atomicCAS(&S.tab[p], kEmpty, key);
-        if (prev == kEmpty || prev == key) return p;
-        p = (p + 1) & S.mask;
+    for (uint32_t s = tid; s < kNextSlots; s += 256) {
+        s_tab[s] = kEmpty;
+        s_cnt[s] = 0;
     }
-}
-
-__device__ __forceinline__ unsigned long long word_mask(uint32_t lo, uint32_t hi) {
-    // bits [lo, hi) of one 64-bit word, 0 <= lo <= hi <= 64
-    const unsigned long long a = lo >= 64 ? 0ull : (~0ull << lo);
-    const unsigned long long b = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
-    return a & b;
-}
-
-// Segment-local bit operations on the LDS copy (positions relative to the
-// segment's first triangle).
-__device__ __forceinline__ void sbits_clear(ChainLds &S, uint32_t lo, uint32_t hi) {
-    const uint32_t w = lane_id();
-    if (lo < hi && w < kSegWords) {
-        const uint32_t a = max(lo, w * 64), b = min(hi, w * 64 + 64);
-        if (a < b) S.sbits[w] &= ~word_mask(a - w * 64, b - w * 64);
+    __syncthreads();
+    // insertion: every thread owns corners tid + 256*k (k < kPer) and probes
+    // them in lockstep rounds so their LDS round trips overlap
+    constexpr uint32_t kBits = 12;   // log2(kNextSlots)
+    constexpr uint32_t kPer = 3 * kNextTris / 256;
+    uint32_t key[kPer], slot[kPer];
+    uint32_t pending = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t i = tid + 256 * k;
+        key[k] = i < n ? s_key[i] : 0u;
+        slot[k] = hash_slot(key[k], kBits);
+        if (i < n) pending |= 1u << k;
     }
-}
-__device__ __forceinline__ bool sbits_test(const ChainLds &S, uint32_t t) { return (S.sbits[t / 64] >> (t % 64)) & 1ull; }
-__device__ __forceinline__ void sbits_set(ChainLds &S, uint32_t t) {
-    if (lane_id() == 0) S.sbits[t / 64] |= 1ull << (t % 64);
-}
-
-// Runs the greedy chain with a batch opened at `start`, over triangles
-// [start, limit) (all staged in the LDS cache).  Every cut c (the start of
-// a new batch, c < limit) is passed to on_cut(c), which returns true to stop
-// the scan there.  Returns the start of the batch open at `limit`, or the
-// stopping cut.  Wave-uniform.
-template <typename OnCut>
-__device__ uint32_t greedy_chain(const PlanArgs &P, ChainLds &S, uint32_t start, uint32_t limit, OnCut on_cut) {
-    const uint32_t lane = lane_id();
-    uint32_t bstart = start, cur = start, distinct = 0;
-    chain_clear_set(S);
-    while (cur < limit) {
-        const uint32_t t = cur + lane;
-        const bool act = t < limit;
-        uint32_t sl0 = 0, sl1 = 0, sl2 = 0;
-        if (act) {
-            const uint32_t *k = S.cache + 3 * (t - S.c0);
-            sl0 = chain_slot(S, k[0]);
-            sl1 = chain_slot(S, k[1]);
-            sl2 = chain_slot(S, k[2]);
+    while (pending) {
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) {
+            if (pending & (1u << k)) {
+                const uint32_t prev = atomicCAS(&s_tab[slot[k]], kEmpty, key[k]);
+                if (prev == kEmpty || prev == key[k]) pending &= ~(1u << k);
+                else slot[k] = (slot[k] + 1) & (kNextSlots - 1);
+            }
         }
-        wave_sync_lds();
-        if (act) {
-            atomicMin(&S.pos[sl0], 3 * t);
-            atomicMin(&S.pos[sl1], 3 * t + 1);
-            atomicMin(&S.pos[sl2], 3 * t + 2);
-        }
-        wave_sync_lds();
-        uint32_t fresh = 0;
-        if (act) fresh = (S.pos[sl0] == 3 * t) + (S.pos[sl1] == 3 * t + 1) + (S.pos[sl2] == 3 * t + 2);
-        const uint32_t incl = wave_incl_scan(fresh);
-        const bool ok = act && distinct + incl <= P.cap && t - bstart + 1 <= P.tmax;
-        const uint32_t acc = (uint32_t)__popcll(ballot(ok));
-        const uint32_t nact = min((uint32_t)kWave, limit - cur);
-        if (acc == nact) {
-            distinct += __builtin_amdgcn_readlane(incl, nact - 1);
-            cur += acc;
-        } else {
-            const uint32_t c = cur + acc;
-            if (on_cut(c)) return c;
-            chain_clear_set(S);   // the triangle at c opens a new batch
-            bstart = c;
-            cur = c;
-            distinct = 0;
-        }
-        wave_sync_lds();
     }
-    return bstart;
-}
-
-__device__ __forceinline__ uint32_t seg_begin(uint32_t s) { return s * kPlanSeg; }
-__device__ __forceinline__ uint32_t seg_end(const PlanArgs &P, uint32_t s) { return min(P.T, (s + 1) * kPlanSeg); }
-
-__device__ __forceinline__ void sbits_store(const PlanArgs &P, const ChainLds &S, uint32_t s) {
-    const uint32_t w = lane_id();
-    const uint32_t gw = s * kSegWords + w;
-    if (w < kSegWords && gw < P.nwords) P.bits[gw] = S.sbits[w];
-}
-
-__device__ __forceinline__ void sbits_load(const PlanArgs &P, ChainLds &S, uint32_t s) {
-    const uint32_t w = lane_id();
-    const uint32_t gw = s * kSegWords + w;
-    if (w < kSegWords) S.sbits[w] = gw < P.nwords ? P.bits[gw] : 0ull;
-}
-
-__global__ __launch_bounds__(64) void k_plan_spec(PlanArgs P) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    ChainLds S = chain_lds(smem, P.hs_bits);
-    const uint32_t s = blockIdx.x;
-    if (s >= P.nseg) return;
-    const uint32_t b = seg_begin(s), e = seg_end(P, s);
-    chain_load(P, S, b, e);
-    if (lane_id() < kSegWords) S.sbits[lane_id()] = 0ull;
-    wave_sync_lds();
-    sbits_set(S, 0);
-    const uint32_t last = greedy_chain(P, S, b, e, [&](uint32_t c) {
-        sbits_set(S, c - b);
-        return false;
-    });
-    wave_sync_lds();
-    sbits_store(P, S, s);
-    if (lane_id() == 0) {
-        P.spec_last[s] = last;
-        P.fix_from[s] = b;       // segment 0 is exact from the start
-        P.fix_last[s] = last;
-    }
-}
-
-// Continues the chain from batch start q (in segment s-1, its batch still
-// open at segment s's first triangle) through s, rewriting s's cut bits up to
-// the first cut s already holds.  The caller has loaded s's bits into LDS.
-__device__ __forceinline__ uint32_t fix_segment(const PlanArgs &P, ChainLds &S, uint32_t s, uint32_t q,
-                                                uint32_t old_last) {
-    const uint32_t b = seg_begin(s), e = seg_end(P, s);
-    chain_load(P, S, q, e);
-    wave_sync_lds();
-    uint32_t clr = 0;
-    bool synced = false;
-    const uint32_t last = greedy_chain(P, S, q, e, [&](uint32_t c) {
-        // c >= b: the batch from q covers every triangle before segment s
-        const uint32_t lc = c - b;
-        const bool had = sbits_test(S, lc);
-        sbits_clear(S, clr, lc);
-        wave_sync_lds();
-        if (had) {
-            synced = true;
-            return true;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t i = tid + 256 * k;
+        if (i < n) {
+            // counts per slot (16-bit LDS words are updated through their 32-bit word)
+            atomicAdd((uint32_t *)&s_cnt[slot[k] & ~1u], (slot[k] & 1u) ? 0x10000u : 1u);
         }
-        sbits_set(S, lc);
-        clr = lc + 1;
-        wave_sync_lds();
-        return false;
-    });
-    if (!synced) sbits_clear(S, clr, e - b);
-    wave_sync_lds();
-    return synced ? old_last : last;
-}
-
-__global__ __launch_bounds__(64) void k_plan_fix(PlanArgs P) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    ChainLds S = chain_lds(smem, P.hs_bits);
-    const uint32_t s = blockIdx.x + 1;
-    if (s >= P.nseg) return;
-    sbits_load(P, S, s);
-    const uint32_t q = P.spec_last[s - 1];
-    const uint32_t last = fix_segment(P, S, s, q, P.spec_last[s]);
-    sbits_store(P, S, s);
-    if (lane_id() == 0) {
-        P.fix_from[s] = q;
-        P.fix_last[s] = last;
     }
-}
-
-// Walk and pack, one workgroup.  A segment s >= 1 is consistent when its fix
-// started from its predecessor's final open batch.  All threads flag the
-// inconsistent segments of a page in LDS; wavefront 0 then visits them in
-// order, redoing each from the true open batch, and re-checks the successor
-// of every redone segment whose open batch changed.  Finally the workgroup
-// compacts the bitmap into the plan, whole segments per thread.
-constexpr uint32_t kWalkPage = 65536;      // segments flagged per pass (8 KB of LDS)
-
-__global__ __launch_bounds__(1024) void k_plan_walk_pack(PlanArgs P) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __shared__ uint32_t tmp[16];
-    __shared__ unsigned long long sbad[kWalkPage / 64];
-    __shared__ uint32_t s_prev_last;
-    if (threadIdx.x == 0) s_prev_last = P.fix_last[0];
-    for (uint32_t page = 0; page * kWalkPage < P.nseg; ++page) {
-        const uint32_t s0 = page * kWalkPage, s1 = min(P.nseg, s0 + kWalkPage);
-        for (uint32_t w = threadIdx.x; w < kWalkPage / 64; w += 1024) sbad[w] = 0ull;
-        __syncthreads();
-        for (uint32_t s = max(s0, 1u) + threadIdx.x; s < s1; s += 1024)
-            if (P.fix_from[s] != P.fix_last[s - 1]) atomicOr(&sbad[(s - s0) / 64], 1ull << ((s - s0) % 64));
-        __syncthreads();
-        if (threadIdx.x < kWave) {
-            ChainLds S = chain_lds(smem, P.hs_bits);
-            uint32_t prev_last = s_prev_last;   // true open batch at the end of segment s0 - 1
-            uint32_t s = max(s0, 1u);
-            bool recheck = page > 0 && s_prev_last != P.fix_last[s0 - 1];
-            if (s0 == 0) prev_last = P.fix_last[0];
-            while (s < s1) {
-                const uint32_t ls = s - s0;
-                const bool flagged = (sbad[ls / 64] >> (ls % 64)) & 1ull;
-                if (!flagged && !recheck) {
-                    // jump to the next flagged segment; everything before it is final
-                    uint32_t nxt = s1;
-                    for (uint32_t w = ls / 64; w < (s1 - s0 + 63) / 64; ++w) {
-                        unsigned long long m = sbad[w];
-                        if (w == ls / 64) m &= ~0ull << (ls % 64);
-                        if (m) {
-                            nxt = s0 + w * 64 + (uint32_t)__ffsll((long long)m) - 1;
-                            break;
+    __syncthreads();
+    {   // bucket starts: exclusive scan of the counts, 16 slots per thread
+        constexpr uint32_t E = kNextSlots / 256;
+        uint32_t sum = 0;
+        for (uint32_t j = 0; j < E; ++j) sum += s_cnt[tid * E + j];
+        uint32_t total;
+        uint32_t run = block_excl_scan<256>(sum, s_tmp, total);
+        for (uint32_t j = 0; j < E; ++j) {
+            const uint32_t cnt = s_cnt[tid * E + j];
+            s_start[tid * E + j] = (uint16_t)run;
+            s_end[tid * E + j] = (uint16_t)run;   // becomes the bucket end (cursor)
+            run += cnt;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t i = tid + 256 * k;
+        if (i < n) {
+            const uint32_t sl = slot[k];
+            const uint32_t old = atomicAdd((uint32_t *)&s_end[sl & ~1u], (sl & 1u) ? 0x10000u : 1u);
+            s_arr[(sl & 1u) ? (old >> 16) : (old & 0xFFFFu)] = (uint16_t)i;
+        }
+    }
+    for (uint32_t c = tid; c <= kNextBlock; c += 256) s_diff[c] = 0;
+    __syncthreads();
+    // previous occurrence of every corner inside the window (bucket order is
+    // arbitrary, so take the largest position below the corner's own), and
+    // the difference array of the full-window distinct counts: corner p is
+    // new to the N_pmax-triangle window starting at c exactly for
+    // prev(p) < 3c <= p < 3c + 3*N_pmax
+    // every thread walks the buckets of its kPer corners in lockstep
+    const uint32_t span = 3 * P.tmax;
+    uint32_t q[kPer], qe[kPer], best[kPer];
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t i = tid + 256 * k;
+        q[k] = i < n ? s_start[slot[k]] : 0u;
+        qe[k] = i < n ? s_end[slot[k]] : 0u;
+        best[k] = kNone;
+    }
+    for (bool more = true; more;) {
+        more = false;
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) {
+            if (q[k] < qe[k]) {
+                const uint32_t i = tid + 256 * k;
+                const uint32_t a = s_arr[q[k]++];
+                if (a < i && (best[k] == kNone || a > best[k])) best[k] = a;
+                more |= q[k] < qe[k];
+            }
+        }
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t i = tid + 256 * k;
+        if (i < n) {
+            ((uint16_t *)s_prev)[4 * (i / 3) + i % 3] = (uint16_t)best[k];
+            const uint32_t lo_prev = best[k] == kNone ? 0u : best[k] / 3 + 1;
+            const uint32_t lo_win = i + 1 > span ? (i + 1 - span + 2) / 3 : 0u;
+            const uint32_t lo = max(lo_prev, lo_win), hi = min(i / 3, kNextBlock - 1);
+            if (lo <= hi) {
+                atomicAdd(&s_diff[lo], 1);
+                atomicAdd(&s_diff[hi + 1], -1);
+            }
+        }
+    }
+    __syncthreads();
+    // full-window distinct count of this lane's start (inclusive scan of the
+    // difference array; each thread owns one start)
+    uint32_t dfull;
+    {
+        uint32_t total;
+        const int d = s_diff[tid];
+        dfull = block_excl_scan<256>((uint32_t)d, s_tmp, total) + (uint32_t)d;
+    }
+    const uint32_t c = c0 + tid;
+    if (c < P.T) {
+        const uint32_t lim = min(P.T, c + P.tmax);
+        uint32_t t = lim;
+        if (dfull > P.cap) {
+            // the budget breaks inside the window: scan for the triangle that
+            // breaks it (kNone + 1 wraps to 0, so a missing previous occurrence
+            // always counts as new)
+            const uint32_t first = 3 * tid;
+            uint32_t distinct = 0;
+            t = c;
+            bool stop = false;
+            while (!stop && t < lim) {
+                unsigned long long pr[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) pr[u] = s_prev[t - c0 + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!stop && t < lim) {
+                        const unsigned long long x = pr[u];
+                        const uint32_t f = ((uint32_t)((x + 1) & 0xFFFF) <= first) +
+                                           ((uint32_t)(((x >> 16) + 1) & 0xFFFF) <= first) +
+                                           ((uint32_t)(((x >> 32) + 1) & 0xFFFF) <= first);
+                        if (distinct + f > P.cap) stop = true;
+                        else {
+                            distinct += f;
+                            ++t;
                         }
                     }
-                    if (nxt >= s1) {
-                        prev_last = P.fix_last[s1 - 1];
-                        s = s1;
-                        break;
-                    }
-                    s = nxt;
-                    prev_last = P.fix_last[s - 1];
-                    continue;
                 }
-                recheck = false;
-                if (P.fix_from[s] != prev_last) {
-                    const uint32_t old_last = P.fix_last[s];
-                    sbits_load(P, S, s);
-                    const uint32_t last = fix_segment(P, S, s, prev_last, old_last);
-                    sbits_store(P, S, s);
-                    if (lane_id() == 0) {
-                        P.fix_from[s] = prev_last;
-                        P.fix_last[s] = last;
-                    }
-                    recheck = last != old_last;   // the successor's start moved
-                    prev_last = last;
-                } else {
-                    prev_last = P.fix_last[s];
-                }
-                ++s;
             }
-            if (lane_id() == 0) s_prev_last = prev_last;
         }
-        __threadfence();
-        __syncthreads();
-        __threadfence();
+        P.next[c] = t;
     }
-    // compaction: thread t owns whole segments [t*E, t*E + E)
+}
+
+// ---------------------------------------------------------------------------
+// 2. Transfer tables.  Table layout: tmax entries of uint16 per range; entry
+// j = the chain's first position at or after the range's start boundary is
+// boundary + j; value = its first position at or after the range's end
+// boundary minus that boundary, or kEnd once the chain has reached T.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_plan_table(PlanArgs P, uint16_t *tab) {
+    extern __shared__ uint32_t s_ptr[];   // seg_len entries
+    constexpr uint32_t kDone = 0x80000000u;
+    const uint32_t s = blockIdx.x;
+    const uint32_t b = seg_lo(P, s), e = seg_hi(P, s), len = e - b;
+    for (uint32_t i = threadIdx.x; i < len; i += 256) {
+        const uint32_t nx = P.next[b + i];
+        s_ptr[i] = nx >= e ? (kDone | (nx - e)) : (nx - b);
+    }
+    __syncthreads();
+    // pointer jumping: every position ends up holding its exit offset
+    uint32_t rounds = 1;
+    while ((1u << rounds) < len) ++rounds;
+    for (uint32_t r = 0; r <= rounds; ++r) {
+        for (uint32_t i = threadIdx.x; i < len; i += 256) {
+            const uint32_t v = s_ptr[i];
+            if (!(v & kDone)) s_ptr[i] = s_ptr[v];
+        }
+        __syncthreads();
+    }
+    for (uint32_t j = threadIdx.x; j < P.tmax; j += 256) {
+        uint16_t out = kEnd;
+        if (j < len) {
+            const uint32_t v = s_ptr[j];
+            const uint32_t exitpos = e + (v & ~kDone);
+            out = exitpos >= P.T ? kEnd : (uint16_t)(exitpos - e);
+        }
+        tab[(size_t)s * P.tmax + j] = out;
+    }
+}
+
+// Composes tables [g*kFanIn, min(count, g*kFanIn + kFanIn)) of `in` into
+// table g of `out`.
+__global__ __launch_bounds__(512) void k_plan_compose(uint32_t tmax, uint32_t count, const uint16_t *in,
+                                                      uint16_t *out) {
+    extern __shared__ uint16_t s_t[];   // kFanIn * tmax
+    const uint32_t g = blockIdx.x;
+    const uint32_t k0 = g * kFanIn, k1 = min(count, k0 + kFanIn);
+    const uint32_t m = (k1 - k0) * tmax;
+    for (uint32_t i = threadIdx.x; i < m; i += 512) s_t[i] = in[(size_t)k0 * tmax + i];
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < tmax; j += 512) {
+        uint32_t x = j;
+        for (uint32_t k = 0; k < k1 - k0 && x != kEnd; ++k) x = s_t[k * tmax + x];
+        out[(size_t)g * tmax + j] = (uint16_t)x;
+    }
+}
+
+// One workgroup: applies the (at most kFanIn) top tables in order starting
+// from entry 0 and records each table's entry.
+__global__ __launch_bounds__(256) void k_plan_top(uint32_t tmax, uint32_t count, const uint16_t *tab,
+                                                  uint16_t *entry) {
+    extern __shared__ uint16_t s_t[];
+    const uint32_t m = count * tmax;
+    for (uint32_t i = threadIdx.x; i < m; i += 256) s_t[i] = tab[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t x = 0;
+        for (uint32_t k = 0; k < count; ++k) {
+            entry[k] = (uint16_t)x;
+            if (x != kEnd) x = s_t[k * tmax + x];
+        }
+    }
+}
+
+// Pushes entries one level down: group g of `tab` (kFanIn tables) receives
+// its entry from up_entry[g] and records its members' entries.
+__global__ __launch_bounds__(256) void k_plan_resolve(uint32_t tmax, uint32_t count, const uint16_t *tab,
+                                                      const uint16_t *up_entry, uint16_t *entry) {
+    extern __shared__ uint16_t s_t[];
+    const uint32_t g = blockIdx.x;
+    const uint32_t k0 = g * kFanIn, k1 = min(count, k0 + kFanIn);
+    const uint32_t m = (k1 - k0) * tmax;
+    for (uint32_t i = threadIdx.x; i < m; i += 256) s_t[i] = tab[(size_t)k0 * tmax + i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t x = up_entry[g];
+        for (uint32_t k = 0; k < k1 - k0; ++k) {
+            entry[k0 + k] = (uint16_t)x;
+            if (x != kEnd) x = s_t[k * tmax + x];
+        }
+    }
+}
+
+// Every segment lists its batch starts: from its entry, follow next().
+__global__ __launch_bounds__(64) void k_plan_emit(PlanArgs P, const uint16_t *entry, uint32_t *cuts,
+                                                  uint32_t *ncuts) {
+    extern __shared__ uint32_t s_next[];   // seg_len entries
+    const uint32_t s = blockIdx.x;
+    const uint32_t b = seg_lo(P, s), e = seg_hi(P, s);
+    for (uint32_t i = threadIdx.x; i < e - b; i += 64) s_next[i] = P.next[b + i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t off = entry[s];
+        uint32_t n = 0;
+        if (off != kEnd) {
+            for (uint32_t x = b + off; x < e; x = s_next[x - b]) cuts[b + n++] = x;
+        }
+        ncuts[s] = n;
+    }
+}
+
+// Packing with one workgroup per segment (draws of at most kPackSegs
+// segments): a segment's offset is the sum of the counts before it, read
+// coalesced; the last segment also writes B and T.
+constexpr uint32_t kPackSegs = 4096;
+
+__global__ __launch_bounds__(64) void k_plan_pack_seg(PlanArgs P, const uint32_t *cuts, const uint32_t *ncuts,
+                                                      uint32_t *plan) {
+    const uint32_t s = blockIdx.x;
+    uint32_t sum = 0;
+    for (uint32_t j = lane_id(); j < s; j += kWave) sum += ncuts[j];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) sum += __shfl_xor(sum, d, kWave);
+    const uint32_t b = seg_lo(P, s), cnt = ncuts[s];
+    for (uint32_t i = lane_id(); i < cnt; i += kWave) plan[1 + sum + i] = cuts[b + i];
+    if (s + 1 == P.nseg && lane_id() == 0) {
+        plan[0] = sum + cnt;
+        plan[1 + sum + cnt] = P.T;
+    }
+}
+
+// Packing for larger draws: one workgroup scans the per-segment counts, then
+// every wavefront copies whole segment lists into the plan.
+__global__ __launch_bounds__(1024) void k_plan_pack(PlanArgs P, const uint32_t *cuts, uint32_t *ncuts,
+                                                    uint32_t *plan) {
+    __shared__ uint32_t tmp[16];
     const uint32_t E = (P.nseg + 1023) / 1024;
     const uint32_t lo = min(P.nseg, threadIdx.x * E), hi = min(P.nseg, lo + E);
-    const uint32_t w0 = lo * kSegWords, w1 = min(P.nwords, hi * kSegWords);
-    uint32_t cnt = 0;
-    for (uint32_t w = w0; w < w1; ++w) cnt += (uint32_t)__popcll(P.bits[w]);
+    uint32_t sum = 0;
+    for (uint32_t s = lo; s < hi; ++s) sum += ncuts[s];
     uint32_t total;
-    uint32_t r = block_excl_scan<1024>(cnt, tmp, total);
-    for (uint32_t w = w0; w < w1; ++w) {
-        unsigned long long m = P.bits[w];
-        while (m) {
-            const uint32_t bit = (uint32_t)__ffsll((long long)m) - 1;
-            P.plan[1 + r++] = w * 64 + bit;
-            m &= m - 1;
-        }
+    uint32_t run = block_excl_scan<1024>(sum, tmp, total);
+    __syncthreads();   // every count is read before any is overwritten
+    for (uint32_t s = lo; s < hi; ++s) {
+        const uint32_t cnt = ncuts[s];
+        ncuts[s] = run;   // becomes the segment's offset in the plan
+        run += cnt;
+    }
+    __threadfence_block();
+    __syncthreads();
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    for (uint32_t s = w; s < P.nseg; s += 1024 / kWave) {
+        const uint32_t b = seg_lo(P, s);
+        // read past the CU's L1: other wavefronts rewrote these words above
+        const uint32_t off = __hip_atomic_load(&ncuts[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t cnt =
+            (s + 1 < P.nseg ? __hip_atomic_load(&ncuts[s + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : total) -
+            off;
+        for (uint32_t i = lane; i < cnt; i += kWave) plan[1 + off + i] = cuts[b + i];
     }
     if (threadIdx.x == 0) {
-        P.plan[0] = total;
-        P.plan[1 + total] = P.T;
+        plan[0] = total;
+        plan[1 + total] = P.T;
     }
 }
 

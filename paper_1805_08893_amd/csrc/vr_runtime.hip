@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "vr.h"
 #include "vr_kernels.h"
@@ -239,39 +240,65 @@ __global__ void k_plan_empty(uint32_t *plan) {
     }
 }
 
-// Builds the plan of a dynamic draw on the context's stream.
+// Builds the plan of a dynamic draw on the context's stream (see vr_plan.h).
 vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, uint32_t nu, uint32_t tmax,
                      uint32_t *d_plan) {
     if (T == 0) {
         hipLaunchKernelGGL(k_plan_empty, dim3(1), dim3(64), 0, c->stream, d_plan);
         return VR_OK;
     }
-    const uint32_t nseg = (T + kPlanSeg - 1) / kPlanSeg;
-    const uint32_t nwords = (T + 63) / 64;
-    const size_t bytes_bits = 8ull * nwords;
-    const size_t bytes_seg = 4ull * nseg;
-    vr_status st = ensure(c, c->plan_work, bytes_bits + 3 * bytes_seg + 256);
+    // segment length: a power of two >= N_pmax, 2048 up to 4M triangles, then
+    // growing to 8192 so that large draws keep a modest number of segments
+    uint32_t L = 2048;
+    while (L < 8192 && (uint64_t)L * 2048 < T) L <<= 1;
+    const uint32_t nseg = (T + L - 1) / L;
+    std::vector<uint32_t> counts{nseg};
+    while (counts.back() > kFanIn) counts.push_back((counts.back() + kFanIn - 1) / kFanIn);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t bytes = al(4ull * T) * 2 + al(4ull * nseg);
+    std::vector<size_t> tab_off, ent_off;
+    for (uint32_t cnt : counts) {
+        tab_off.push_back(bytes);
+        bytes += al(2ull * cnt * tmax);
+        ent_off.push_back(bytes);
+        bytes += al(2ull * cnt);
+    }
+    vr_status st = ensure(c, c->plan_work, bytes);
     if (st != VR_OK) return st;
     unsigned char *base = (unsigned char *)c->plan_work.ptr;
+    uint32_t *next = (uint32_t *)base;
+    uint32_t *cuts = (uint32_t *)(base + al(4ull * T));
+    uint32_t *ncuts = (uint32_t *)(base + 2 * al(4ull * T));
+    auto tab = [&](size_t l) { return (uint16_t *)(base + tab_off[l]); };
+    auto ent = [&](size_t l) { return (uint16_t *)(base + ent_off[l]); };
     PlanArgs P{};
     P.idx = d_idx;
     P.V = V;
     P.T = T;
     P.cap = nu;
     P.tmax = tmax;
+    P.seg_len = L;
     P.nseg = nseg;
-    P.nwords = nwords;
-    P.hs_bits = log2u(2 * (nu + 192));
-    P.bits = (unsigned long long *)base;
-    P.spec_last = (uint32_t *)(base + bytes_bits);
-    P.fix_from = P.spec_last + nseg;
-    P.fix_last = P.fix_from + nseg;
-    P.plan = d_plan;
+    P.next = next;
     P.err = &c->d_words->err;
-    const uint32_t lds = plan_chain_lds(P.hs_bits);
-    hipLaunchKernelGGL(k_plan_spec, dim3(nseg), dim3(64), lds, c->stream, P);
-    if (nseg > 1) hipLaunchKernelGGL(k_plan_fix, dim3(nseg - 1), dim3(64), lds, c->stream, P);
-    hipLaunchKernelGGL(k_plan_walk_pack, dim3(1), dim3(1024), lds, c->stream, P);
+    hipLaunchKernelGGL(k_plan_next, dim3((T + kNextBlock - 1) / kNextBlock), dim3(256), 0, c->stream, P);
+    hipLaunchKernelGGL(k_plan_table, dim3(nseg), dim3(256), 4 * L, c->stream, P, tab(0));
+    const uint32_t grp_lds = 2 * kFanIn * tmax;
+    for (size_t l = 0; l + 1 < counts.size(); ++l)
+        hipLaunchKernelGGL(k_plan_compose, dim3(counts[l + 1]), dim3(512), grp_lds, c->stream, tmax, counts[l],
+                           (const uint16_t *)tab(l), tab(l + 1));
+    const size_t top = counts.size() - 1;
+    hipLaunchKernelGGL(k_plan_top, dim3(1), dim3(256), 2 * counts[top] * tmax, c->stream, tmax, counts[top],
+                       (const uint16_t *)tab(top), ent(top));
+    for (size_t l = top; l-- > 0;)
+        hipLaunchKernelGGL(k_plan_resolve, dim3(counts[l + 1]), dim3(256), grp_lds, c->stream, tmax, counts[l],
+                           (const uint16_t *)tab(l), (const uint16_t *)ent(l + 1), ent(l));
+    hipLaunchKernelGGL(k_plan_emit, dim3(nseg), dim3(64), 4 * L, c->stream, P, (const uint16_t *)ent(0), cuts, ncuts);
+    if (nseg <= kPackSegs)
+        hipLaunchKernelGGL(k_plan_pack_seg, dim3(nseg), dim3(64), 0, c->stream, P, (const uint32_t *)cuts,
+                           (const uint32_t *)ncuts, d_plan);
+    else
+        hipLaunchKernelGGL(k_plan_pack, dim3(1), dim3(1024), 0, c->stream, P, (const uint32_t *)cuts, ncuts, d_plan);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
 }
