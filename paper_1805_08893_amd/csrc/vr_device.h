@@ -152,6 +152,37 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
     return before + incl - v;
 }
 
+// Workgroup-wide min / max (contain barriers: call uniformly).
+template <int NT>
+__device__ __forceinline__ uint32_t block_reduce_min(uint32_t v, uint32_t *tmp) {
+    constexpr int NW = NT / kWave;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = min(v, (uint32_t)__shfl_xor(v, d, kWave));
+    __syncthreads();
+    if (lane_id() == 0) tmp[threadIdx.x / kWave] = v;
+    __syncthreads();
+    uint32_t r = tmp[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) r = min(r, tmp[i]);
+    __syncthreads();
+    return r;
+}
+
+template <int NT>
+__device__ __forceinline__ uint32_t block_reduce_max(uint32_t v, uint32_t *tmp) {
+    constexpr int NW = NT / kWave;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = max(v, (uint32_t)__shfl_xor(v, d, kWave));
+    __syncthreads();
+    if (lane_id() == 0) tmp[threadIdx.x / kWave] = v;
+    __syncthreads();
+    uint32_t r = tmp[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) r = max(r, tmp[i]);
+    __syncthreads();
+    return r;
+}
+
 // --------------------------------------------------------------------------
 // Single-pass prefix over units (decoupled look-back).  A status word is
 //   [63:62] flag (0 = not ready, 1 = aggregate, 2 = inclusive prefix)

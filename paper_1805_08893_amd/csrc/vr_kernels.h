@@ -215,7 +215,7 @@ __host__ __device__ inline DedupLds dedup_lds_layout(int mode, uint32_t max_idx,
     L.keys = off;  off += align16(4 * max_idx);
     L.local = off; off += align16(4 * max_idx);
     if (mode == kSort) {
-        L.pairs = off; off += 8 * pow2_ceil(max_idx);
+        L.pairs = off; off += align16(4 * max_idx);   // two uint16 position buffers
         L.table = L.first = 0;
     } else {
         L.pairs = 0;
@@ -223,30 +223,14 @@ __host__ __device__ inline DedupLds dedup_lds_layout(int mode, uint32_t max_idx,
         L.first = off; off += align16(4u << hash_bits);
     }
     L.uniq = off; off += align16(4 * max_uniq);
-    L.sv = off;   off += 48 * max_uniq;
+    L.sv = off;
+    // the sort's digit-count table (256 digits x rounds x waves, uint16) lives
+    // in the shaded-vertex area before shading
+    // (rounds x waves <= ceil(max_idx / 64) + 8 for any workgroup of <= 512)
+    off += mode == kSort ? max(48 * max_uniq, 2u * 256u * ((max_idx + 63) / 64 + 8)) : 48 * max_uniq;
     L.tmp = off;  off += 64;
     L.total = off;
     return L;
-}
-
-// Bitonic sort of n2 (a power of two) 64-bit keys in LDS.
-template <int NT>
-__device__ __forceinline__ void lds_bitonic_sort(unsigned long long *a, uint32_t n2) {
-    for (uint32_t k = 2; k <= n2; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < n2 / 2; i += NT) {
-                const uint32_t lo = 2 * i - (i & (j - 1));
-                const uint32_t hi = lo + j;
-                const bool up = (lo & k) == 0;
-                const unsigned long long x = a[lo], y = a[hi];
-                if ((x > y) == up) {
-                    a[lo] = y;
-                    a[hi] = x;
-                }
-            }
-            __syncthreads();
-        }
-    }
 }
 
 // Ranks flagged entries of a unit in index order with a blocked scan:
@@ -309,26 +293,92 @@ __global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh) {
 
         uint32_t inv;
         if (MODE == kSort) {
-            unsigned long long *s_pairs = (unsigned long long *)(smem + L.pairs);
-            const uint32_t n2 = pow2_ceil(max(n, 2u));
+            // LSD radix sort of the positions by index (Algorithm 2's sort):
+            // 8-bit digits of (index - batch minimum), only as many passes as
+            // the batch's index range needs.  Within a pass, element x of the
+            // current order is handled in round x / NT by thread x % NT; its
+            // stable destination is the digit's offset for (round, wave) plus
+            // its rank among the wavefront's lanes with the same digit, found
+            // with 8 ballots.
+            uint16_t *s_pos0 = (uint16_t *)(smem + L.pairs);
+            uint16_t *s_pos1 = s_pos0 + A.max_idx;
+            uint16_t *s_cnt = (uint16_t *)(smem + L.sv);   // free until shading
+            constexpr uint32_t NW = NT / kWave;
+            const uint32_t R = (n + NT - 1) / NT;   // <= 8: the launcher sizes NT >= max_idx / 8
             __syncthreads();
-            for (uint32_t i = tid; i < n2; i += NT)
-                s_pairs[i] = i < n ? ((unsigned long long)s_keys[i] << 32) | i : ~0ull;
+            uint32_t kmin = kEmpty, kmax = 0;
+            for (uint32_t i = tid; i < n; i += NT) {
+                const uint32_t k = s_keys[i];
+                kmin = min(kmin, k);
+                kmax = max(kmax, k);
+                s_pos0[i] = (uint16_t)i;
+            }
+            kmin = block_reduce_min<NT>(kmin, s_tmp);
+            kmax = block_reduce_max<NT>(kmax, s_tmp);
+            const uint32_t span = n ? kmax - kmin : 0u;
+            const uint32_t passes = span ? (32u - __builtin_clz(span) + 7u) / 8u : 0u;
+            const uint32_t w = tid / kWave;
+            uint16_t *src = s_pos0, *dst = s_pos1;
+            for (uint32_t pass = 0; pass < passes; ++pass) {
+                const uint32_t M = 256u * R * NW;
+                for (uint32_t i = tid; i < M; i += NT) s_cnt[i] = 0;
+                __syncthreads();
+                uint32_t dig[8], rank[8], pos[8];
+                for (uint32_t r = 0; r < R; ++r) {
+                    const uint32_t x = r * NT + tid;
+                    const bool act = x < n;
+                    const uint32_t p = act ? src[x] : 0u;
+                    const uint32_t d = act ? ((s_keys[p] - kmin) >> (8 * pass)) & 0xFFu : 0u;
+                    uint64_t peers = ballot(act);
+#pragma unroll
+                    for (int bit = 0; bit < 8; ++bit) {
+                        const uint64_t m = ballot((d >> bit) & 1u);
+                        peers &= ((d >> bit) & 1u) ? m : ~m;
+                    }
+                    const uint32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+                    if (act && rk == 0) s_cnt[(d * R + r) * NW + w] = (uint16_t)__popcll(peers);
+                    dig[r] = d;
+                    rank[r] = rk;
+                    pos[r] = p;
+                }
+                __syncthreads();
+                {   // exclusive scan of the counts in (digit, round, wave) order
+                    const uint32_t E = (M + NT - 1) / NT;
+                    const uint32_t lo = min(M, tid * E), hi = min(M, lo + E);
+                    uint32_t sum = 0;
+                    for (uint32_t i = lo; i < hi; ++i) sum += s_cnt[i];
+                    uint32_t total;
+                    uint32_t run = block_excl_scan<NT>(sum, s_tmp, total);
+                    for (uint32_t i = lo; i < hi; ++i) {
+                        const uint32_t c = s_cnt[i];
+                        s_cnt[i] = (uint16_t)run;
+                        run += c;
+                    }
+                }
+                __syncthreads();
+                for (uint32_t r = 0; r < R; ++r) {
+                    const uint32_t x = r * NT + tid;
+                    if (x < n) dst[s_cnt[(dig[r] * R + r) * NW + w] + rank[r]] = (uint16_t)pos[r];
+                }
+                __syncthreads();
+                uint16_t *t = src;
+                src = dst;
+                dst = t;
+            }
+            // run ends of the sorted indices; the exclusive prefix over run
+            // ends is the rank of every entry's run (Algorithm 2's marks and
+            // prefix sum)
             __syncthreads();
-            lds_bitonic_sort<NT>(s_pairs, n2);
-            // run ends of the sorted keys; the exclusive prefix over run ends
-            // is the rank of every entry's run (Algorithm 2's marks / prefix)
             const uint32_t E = (n + NT - 1) / NT;
             const uint32_t lo = min(n, tid * E), hi = min(n, lo + E);
             uint32_t cnt = 0;
-            for (uint32_t i = lo; i < hi; ++i)
-                cnt += (i + 1 == n || (uint32_t)(s_pairs[i] >> 32) != (uint32_t)(s_pairs[i + 1] >> 32));
+            for (uint32_t i = lo; i < hi; ++i) cnt += (i + 1 == n || s_keys[src[i]] != s_keys[src[i + 1]]);
             uint32_t r = block_excl_scan<NT>(cnt, s_tmp, inv);
             for (uint32_t i = lo; i < hi; ++i) {
-                const unsigned long long p = s_pairs[i];
-                s_local[(uint32_t)p] = r;
-                if (i + 1 == n || (uint32_t)(p >> 32) != (uint32_t)(s_pairs[i + 1] >> 32))
-                    s_uniq[r++] = (uint32_t)(p >> 32);
+                const uint32_t p = src[i], k = s_keys[p];
+                s_local[p] = r;
+                if (i + 1 == n || k != s_keys[src[i + 1]]) s_uniq[r++] = k;
             }
         } else {
             uint32_t *s_table = (uint32_t *)(smem + L.table);

@@ -183,6 +183,9 @@ vr_status check_args(vr_ctx *c, uint64_t num_indices, const vr_shader_params *sh
         uint32_t want = o.wg_size ? o.wg_size : std::max<uint32_t>(64, std::min<uint32_t>(256, r.max_uniq));
         uint32_t nt = 64;
         while (nt * 2 <= want && nt < 512) nt *= 2;
+        // the sort keeps at most 8 rounds of elements per thread in registers
+        if (strategy == VR_STATIC_SORT || strategy == VR_DYN_SORT)
+            while (nt * 8 < r.max_idx) nt *= 2;
         r.nt = nt;
         const uint32_t slots = o.hash_slots ? o.hash_slots : std::max<uint32_t>(8, 1u << log2u(2 * r.max_uniq));
         r.hash_bits = log2u(slots);
