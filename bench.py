@@ -14,6 +14,8 @@ reported beside it, with the roofline of the dominant kernel and the CPU
 oracle timed on a bounded sample.
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +31,10 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 METRIC = "triangles/s & shading rate per strategy vs no-reuse; p50/p99 draw latency"
 
+# main kernel of each draw in the step (Phong shading instantiation)
+KERNEL_NAMES = {"naive": "k_naive<1>", "static_ballot": "k_ballot<1>", "dyn_sort": "k_dedup<256, 0, 1>",
+                "dyn_hash": "k_dedup<256, 1, 1>", "dyn_phash": "k_dedup<256, 2, 1>"}
+
 
 def shader_flops(sp):
     """FP32 operations of one vertex-program evaluation (fma = 2, sqrt and
@@ -39,6 +45,33 @@ def shader_flops(sp):
     if sp.kind == 2:
         return mvp + 11 + 9 * sp.iterations
     return mvp
+
+
+def kernel_source_sha():
+    """Hash of the kernel sources: HBM-traffic counters are used only when they
+    were taken on exactly these sources."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1805_08893_amd", "csrc", "*"))) + \
+        [os.path.join(ROOT, "include", "vr.h")]
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
 
 
 def main():
@@ -126,12 +159,16 @@ def main():
     names = ["plan"] + [s[0] for s in strategies]
     ev = [{n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for n in names}
           for _ in range(args.steps)]
+    vr.vr_set_kernel_timing(stage.ctx, True)
+    vr.vr_kernel_times(stage.ctx)           # start from an empty record
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(ev[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ktimes = np.array(vr.vr_kernel_times(stage.ctx), dtype=np.float64).reshape(args.steps, len(names))
+    vr.vr_set_kernel_timing(stage.ctx, False)
     st, inv_total = stage.sync()
     stage.check(st)
 
@@ -139,10 +176,10 @@ def main():
     tris_step = T * len(strategies)
     value = tris_step / (ms_step * 1e-3)
     per = {}
-    for n in names:
+    for j, n in enumerate(names):
         ms = [ev[k][n][0].elapsed_time(ev[k][n][1]) for k in range(args.steps)]
         per[n] = {"ms_mean": float(np.mean(ms)), "ms_p50": float(np.percentile(ms, 50)),
-                  "ms_p99": float(np.percentile(ms, 99))}
+                  "ms_p99": float(np.percentile(ms, 99)), "kernel_ms_mean": float(ktimes[:, j].mean())}
     for name, s, bt, _ in strategies:
         inv = int(res[name]["counters"][0].item())
         p = per[name]
@@ -151,9 +188,10 @@ def main():
     for name, *_ in strategies:
         per[name]["speedup_vs_naive"] = (per["naive"]["ms_mean"] / per[name]["ms_mean"]) if "naive" in per else None
 
-    # dominant kernel: the slowest draw of the step
-    dom = max((s[0] for s in strategies), key=lambda n: per[n]["ms_mean"])
-    dom_ms = per[dom]["ms_mean"]
+    # dominant kernel: the main kernel of the slowest draw of the step, timed
+    # with HIP events around its launch on the library's stream
+    dom = max((s[0] for s in strategies), key=lambda n: per[n]["kernel_ms_mean"])
+    dom_ms = per[dom]["kernel_ms_mean"]
     alg_bytes = 12 * T + 32 * U + 144 * T            # indices + each referenced vertex once + corners
     alg_flops = per[dom]["invocations"] * shader_flops(sp)
     gbs = alg_bytes / (dom_ms * 1e-3) / 1e9
@@ -163,9 +201,10 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": tfl, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": tfl / FP32_VECTOR_PEAK_TFLOPS}
-    roof.update({"traffic": None, "kernel": dom, "bytes_per_launch": alg_bytes, "flops_per_launch": alg_flops,
-                 "ms_per_launch": dom_ms, "hbm_frac": gbs / HBM_PEAK_GBS,
-                 "alu_frac": tfl / FP32_VECTOR_PEAK_TFLOPS})
+    roof.update({"traffic": committed_traffic(KERNEL_NAMES[dom]), "kernel": KERNEL_NAMES[dom], "draw": dom,
+                 "bytes_per_launch": alg_bytes, "flops_per_launch": alg_flops, "ms_per_launch": dom_ms,
+                 "hbm_frac": gbs / HBM_PEAK_GBS, "alu_frac": tfl / FP32_VECTOR_PEAK_TFLOPS,
+                 "kernel_source_sha": kernel_source_sha()})
 
     cpu = None
     if not args.no_cpu:

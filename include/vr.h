@@ -196,6 +196,18 @@ vr_status vr_process_draw(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_i
  * NULL, the vertex-shader invocations of all draws since then. */
 vr_status vr_sync(vr_ctx *ctx, uint64_t *h_invocations);
 
+/*
+ * Kernel timing (a measurement aid, off by default).  While enabled, every
+ * vr_process_draw records a pair of HIP events on the context's stream
+ * around its main kernel, and every vr_plan_dynamic around its kernels.
+ * vr_kernel_times waits for the stream and returns the elapsed milliseconds
+ * of the launches recorded since its previous call, in submission order
+ * (at most `cap`; *count receives how many were recorded, which may exceed
+ * cap), then forgets them.
+ */
+vr_status vr_set_kernel_timing(vr_ctx *ctx, int enable);
+vr_status vr_kernel_times(vr_ctx *ctx, float *ms, uint32_t cap, uint32_t *count);
+
 /* Text of the last error on ctx (or of the last vr_create failure when ctx
  * is NULL).  Valid until the next call on the same context. */
 const char *vr_last_error(const vr_ctx *ctx);

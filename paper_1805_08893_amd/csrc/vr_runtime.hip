@@ -44,6 +44,9 @@ struct vr_ctx {
     CtxWords *d_words = nullptr;
     Scratch status, agg, plan, plan_work;
     uint32_t host_err = 0;   // data error found on the host, reported by vr_sync
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;   // reused event pairs
+    size_t ev_used = 0;
 };
 
 namespace {
@@ -98,6 +101,28 @@ vr_status ensure(vr_ctx *c, Scratch &s, size_t bytes, bool zero = false) {
     if (zero) VR_HIP(c, hipMemsetAsync(s.ptr, 0, bytes, c->stream));
     return VR_OK;
 }
+
+// Event pair around the next launches when kernel timing is on.
+struct TimedRegion {
+    vr_ctx *c;
+    hipEvent_t stop = nullptr;
+    explicit TimedRegion(vr_ctx *ctx) : c(ctx) {
+        if (!c->timing) return;
+        if (c->ev_used == c->ev_pool.size()) {
+            hipEvent_t a = nullptr, b = nullptr;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+            c->ev_pool.push_back({a, b});
+        }
+        auto &pr = c->ev_pool[c->ev_used++];
+        (void)hipEventRecord(pr.first, c->stream);
+        stop = pr.second;
+    }
+    void done() {
+        if (stop) (void)hipEventRecord(stop, c->stream);
+        stop = nullptr;
+    }
+    ~TimedRegion() { done(); }
+};
 
 bool is_dynamic(vr_strategy s) { return s >= VR_DYN_SORT && s <= VR_DYN_BALLOT; }
 bool is_ballot(vr_strategy s) { return s == VR_STATIC_BALLOT || s == VR_DYN_BALLOT; }
@@ -284,6 +309,7 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     P.nseg = nseg;
     P.next = next;
     P.err = &c->d_words->err;
+    TimedRegion timed(c);
     hipLaunchKernelGGL(k_plan_next, dim3((T + kNextBlock - 1) / kNextBlock), dim3(256), 0, c->stream, P);
     hipLaunchKernelGGL(k_plan_table, dim3(nseg), dim3(256), 4 * L, c->stream, P, tab(0));
     const uint32_t grp_lds = 2 * kFanIn * tmax;
@@ -344,6 +370,10 @@ void vr_destroy(vr_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     for (Scratch *s : {&c->status, &c->agg, &c->plan, &c->plan_work})
         if (s->ptr) (void)hipFree(s->ptr);
+    for (auto &pr : c->ev_pool) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
     if (c->d_words) (void)hipFree(c->d_words);
     delete c;
 }
@@ -425,6 +455,7 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
 
     const vr_shader_params &sh = *shader;
     if (strategy == VR_NAIVE) {
+        TimedRegion timed(c);
         if (sh.kind == 0) launch_naive<0>(c, A, sh);
         else if (sh.kind == 1) launch_naive<1>(c, A, sh);
         else launch_naive<2>(c, A, sh);
@@ -464,6 +495,7 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
         A.status = nullptr;
         A.status_cap = (uint32_t)nb_bound;
     }
+    TimedRegion timed(c);
     if (is_ballot(strategy)) {
         const uint32_t lds = 64 * 48 + ((3 * batch_tris + 15) & ~15u);
         if (sh.kind == 0) launch_ballot<0>(c, A, sh, lds, nb_bound);
@@ -481,6 +513,7 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
         else if (mode == kHash) dispatch_kind<kHash>(c, sh.kind, r.nt, A, sh, lds, nb_bound);
         else dispatch_kind<kPHash>(c, sh.kind, r.nt, A, sh, lds, nb_bound);
     }
+    timed.done();
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, c->stream, A.plan, A.num_batches, A.status_cap,
                        (const unsigned long long *)A.agg, A.status, A.counters, A.total_inv);
     VR_HIP(c, hipGetLastError());
@@ -499,6 +532,24 @@ vr_status vr_sync(vr_ctx *c, uint64_t *h_invocations) {
     c->host_err = 0;
     if (e == VR_ERR_INDEX_RANGE) return fail(c, VR_ERR_INDEX_RANGE, "an index is >= num_vertices");
     if (e != 0) return fail(c, (vr_status)e, "device-side error %u", e);
+    return VR_OK;
+}
+
+vr_status vr_set_kernel_timing(vr_ctx *c, int enable) {
+    if (!c) return VR_ERR_ARG;
+    c->timing = enable != 0;
+    return VR_OK;
+}
+
+vr_status vr_kernel_times(vr_ctx *c, float *ms, uint32_t cap, uint32_t *count) {
+    if (!c) return VR_ERR_ARG;
+    DeviceGuard g(c->device);
+    VR_HIP(c, hipStreamSynchronize(c->stream));
+    const size_t n = c->ev_used;
+    for (size_t i = 0; i < n && i < cap && ms; ++i)
+        VR_HIP(c, hipEventElapsedTime(&ms[i], c->ev_pool[i].first, c->ev_pool[i].second));
+    if (count) *count = (uint32_t)n;
+    c->ev_used = 0;
     return VR_OK;
 }
 

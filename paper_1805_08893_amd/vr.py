@@ -27,7 +27,7 @@ DYNAMIC = (VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH, VR_DYN_BALLOT)
 OUT_FLOATS = 12
 
 EXPORTS = ["vr_create", "vr_destroy", "vr_set_stream", "vr_check_args", "vr_plan_dynamic", "vr_process_draw",
-           "vr_sync", "vr_last_error"]
+           "vr_sync", "vr_set_kernel_timing", "vr_kernel_times", "vr_last_error"]
 
 
 class vr_opts(C.Structure):
@@ -83,6 +83,10 @@ def lib():
         L.vr_process_draw.restype = C.c_int
         L.vr_sync.argtypes = [P, C.POINTER(C.c_uint64)]
         L.vr_sync.restype = C.c_int
+        L.vr_set_kernel_timing.argtypes = [P, C.c_int]
+        L.vr_set_kernel_timing.restype = C.c_int
+        L.vr_kernel_times.argtypes = [P, C.POINTER(C.c_float), C.c_uint32, C.POINTER(C.c_uint32)]
+        L.vr_kernel_times.restype = C.c_int
         L.vr_last_error.argtypes = [P]
         L.vr_last_error.restype = C.c_char_p
         _lib = L
@@ -165,6 +169,20 @@ def vr_sync(ctx):
     inv = C.c_uint64(0)
     st = lib().vr_sync(ctx, C.byref(inv))
     return st, int(inv.value)
+
+
+def vr_set_kernel_timing(ctx, enable):
+    return lib().vr_set_kernel_timing(ctx, 1 if enable else 0)
+
+
+def vr_kernel_times(ctx, cap=4096):
+    """Milliseconds of the timed launches since the previous call, in order."""
+    buf = (C.c_float * cap)()
+    n = C.c_uint32(0)
+    st = lib().vr_kernel_times(ctx, buf, cap, C.byref(n))
+    if st != VR_OK:
+        raise VrError(st, vr_last_error(ctx))
+    return [buf[i] for i in range(min(n.value, cap))]
 
 
 # ---------------------------------------------------------------- convenience
