@@ -197,9 +197,53 @@ vr_status vr_process_draw(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_i
 vr_status vr_sync(vr_ctx *ctx, uint64_t *h_invocations);
 
 /*
+ * Frames: many draws in one persistent launch (the streaming geometry stage
+ * of Section 4.2 applied to a list of draws of uneven size).  Each draw is
+ * processed exactly as vr_process_draw would process it with only `corners`
+ * and `counters` requested, so every draw keeps its own batches, ids and
+ * invocation counts.  Dynamic draws need their plan (vr_plan_dynamic with the
+ * same indices, max_unique and batch_tris) in d_plan.
+ */
+typedef struct vr_frame vr_frame;
+
+typedef struct {
+    const uint32_t *d_indices;   /* uint32[num_indices]                            */
+    uint64_t num_indices;
+    const float *d_vertices;     /* float32[num_vertices][8], 16-byte aligned      */
+    uint32_t num_vertices;
+    uint32_t shader;             /* index into the frame's shader table            */
+    vr_strategy strategy;
+    uint32_t batch_tris;         /* as for vr_process_draw                         */
+    uint32_t max_unique;         /* DYN_*: N_u, 0 = default                        */
+    const uint32_t *d_plan;      /* DYN_*: required; ignored otherwise             */
+    float *d_corners;            /* float32[3T][12], required, 16-byte aligned     */
+    uint64_t *d_counters;        /* uint64[4] {invocations, units, 0, 0} or NULL   */
+} vr_draw;
+
+#define VR_MAX_FRAME_DRAWS 4096
+
+/* Validate and upload a frame (draw and shader tables are copied to device
+ * memory owned by the frame; the device buffers named in the draws must stay
+ * valid while the frame exists).  With capture_graph != 0 the frame's
+ * launches are captured once into a hipGraph that vr_frame_run replays.
+ * Returns VR_ERR_ARG for more than VR_MAX_FRAME_DRAWS draws, a shader index
+ * out of range, a dynamic draw without a plan, or any per-draw argument error
+ * (vr_last_error names the draw). */
+vr_status vr_frame_create(vr_ctx *ctx, const vr_draw *draws, uint32_t num_draws, const vr_shader_params *shaders,
+                          uint32_t num_shaders, int capture_graph, vr_frame **frame);
+/* Enqueue the frame on its context's stream (a graph launch when captured). */
+vr_status vr_frame_run(vr_frame *frame);
+/* Wait for the context's stream and release the frame. */
+void vr_frame_destroy(vr_frame *frame);
+/* One-shot frame: create, run, wait and destroy (synchronous). */
+vr_status vr_process_draws(vr_ctx *ctx, const vr_draw *draws, uint32_t num_draws, const vr_shader_params *shaders,
+                           uint32_t num_shaders);
+
+/*
  * Kernel timing (a measurement aid, off by default).  While enabled, every
  * vr_process_draw records a pair of HIP events on the context's stream
- * around its main kernel, and every vr_plan_dynamic around its kernels.
+ * around its main kernel, every vr_plan_dynamic around its kernels and every
+ * vr_frame_run around the whole frame.
  * vr_kernel_times waits for the stream and returns the elapsed milliseconds
  * of the launches recorded since its previous call, in submission order
  * (at most `cap`; *count receives how many were recorded, which may exceed

@@ -113,6 +113,13 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Orders this wavefront's LDS accesses before and after the call.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Inclusive scan over the 64 lanes with DPP: Hillis-Steele steps of 1, 2, 4
 // and 8 lanes inside each 16-lane row, then row 0's and row 2's totals are
 // broadcast into rows 1 and 3 (row_bcast:15) and the total of rows 0-1 into

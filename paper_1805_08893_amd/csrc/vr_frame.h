@@ -1,0 +1,197 @@
+// Many draws in one persistent launch (a frame).
+//
+// The streaming pipeline of the paper processes the index buffer batch by
+// batch (Sections 3 and 4.2); a frame applies that to a list of draws of
+// uneven size at once.  Every draw keeps exactly the units the single-draw
+// path computes: static batches, dynamic batches from its plan, ballot
+// batches (one wavefront each) or naive chunks of 256 corners.  A prepare
+// kernel counts each draw's units and prefix-sums them into one unit space;
+// the persistent kernel deals that space out to its workgroups in chunks of
+// kFrameChunk units, round robin, finds each unit's draw by binary search in
+// an LDS copy of the draw bases, and dispatches on the draw's dedup mode and
+// shader kind.  Per-unit aggregates are reduced per draw afterwards, so no
+// same-address atomics are on the hot path.
+#pragma once
+
+#include "vr_kernels.h"
+
+namespace vr {
+
+enum FrameMode : uint32_t { kFrameSort = 0, kFrameHash = 1, kFramePHash = 2, kFrameBallot = 3, kFrameNaive = 4 };
+constexpr uint32_t kFrameNT = 256;
+constexpr uint32_t kFrameChunk = 4;      // consecutive units a workgroup takes at a time
+constexpr uint32_t kFrameMaxDraws = 4096;
+
+struct DrawDesc {
+    const uint32_t *idx;
+    const f4 *vtx;
+    f4 *corners;
+    unsigned long long *counters;
+    const uint32_t *plan;
+    uint32_t V, T, batch_tris, num_batches;
+    uint32_t shader, mode, kind;
+    uint32_t max_idx, max_uniq, hash_bits, probes;
+};
+
+// Units (workgroup tasks) and aggregate slots of a draw.
+__device__ __forceinline__ void frame_draw_units(const DrawDesc &D, uint32_t &units, uint32_t &slots) {
+    if (D.mode == kFrameNaive) {
+        units = slots = (uint32_t)((3ull * D.T + 255) / 256);
+        return;
+    }
+    const uint32_t nb = D.T == 0 ? 0u : (D.plan ? D.plan[0] : D.num_batches);
+    slots = nb;
+    units = D.mode == kFrameBallot ? (nb + 3) / 4 : nb;   // four wavefronts, four ballot batches
+}
+
+// One workgroup: per-draw unit and slot bases (exclusive scans), totals last.
+__global__ __launch_bounds__(1024) void k_frame_prepare(const DrawDesc *draws, uint32_t n, uint32_t *unit_base,
+                                                        uint32_t *slot_base) {
+    __shared__ uint32_t tmp[16];
+    const uint32_t E = (n + 1023) / 1024;
+    const uint32_t lo = min(n, threadIdx.x * E), hi = min(n, lo + E);
+    uint32_t su = 0, ss = 0;
+    for (uint32_t d = lo; d < hi; ++d) {
+        uint32_t u, s;
+        frame_draw_units(draws[d], u, s);
+        su += u;
+        ss += s;
+    }
+    uint32_t tu, ts;
+    uint32_t ru = block_excl_scan<1024>(su, tmp, tu);
+    uint32_t rs = block_excl_scan<1024>(ss, tmp, ts);
+    for (uint32_t d = lo; d < hi; ++d) {
+        uint32_t u, s;
+        frame_draw_units(draws[d], u, s);
+        unit_base[d] = ru;
+        slot_base[d] = rs;
+        ru += u;
+        rs += s;
+    }
+    if (threadIdx.x == 0) {
+        unit_base[n] = tu;
+        slot_base[n] = ts;
+    }
+}
+
+__device__ __forceinline__ DrawArgs frame_args(const DrawDesc &D, unsigned long long *agg, uint32_t *err,
+                                               unsigned long long *total_inv) {
+    DrawArgs A{};
+    A.idx = D.idx;
+    A.vtx = D.vtx;
+    A.V = D.V;
+    A.T = D.T;
+    A.batch_tris = D.batch_tris;
+    A.num_batches = D.num_batches;
+    A.plan = D.plan;
+    A.corners = D.corners;
+    A.agg = agg;
+    A.err = err;
+    A.total_inv = total_inv;
+    A.hash_bits = D.hash_bits;
+    A.probes = D.probes;
+    A.max_idx = D.max_idx;
+    A.max_uniq = D.max_uniq;
+    A.need_prefix = 0;
+    A.status_cap = 0xFFFFFFFFu;
+    return A;
+}
+
+template <int KIND>
+__device__ __forceinline__ void frame_unit_kind(const DrawDesc &D, const DrawArgs &A, const vr_shader_params &sh,
+                                                uint32_t local, uint32_t nb, unsigned char *smem,
+                                                uint32_t ballot_stride) {
+    switch (D.mode) {
+    case kFrameSort: dedup_unit<kFrameNT, kSort, KIND>(A, sh, local, nb, smem); break;
+    case kFrameHash: dedup_unit<kFrameNT, kHash, KIND>(A, sh, local, nb, smem); break;
+    case kFramePHash: dedup_unit<kFrameNT, kPHash, KIND>(A, sh, local, nb, smem); break;
+    case kFrameBallot: {
+        const uint32_t w = threadIdx.x / kWave;
+        const uint32_t b = 4 * local + w;
+        unsigned char *mine = smem + w * ballot_stride;
+        if (b < nb) ballot_batch<KIND>(A, sh, b, nb, (f4 *)mine, mine + 64 * 48);
+        __syncthreads();
+        break;
+    }
+    default: {
+        const unsigned long long agg = naive_chunk<KIND>(A, sh, local, (f4 *)smem);
+        if (threadIdx.x == 0) A.agg[local] = agg;
+        break;
+    }
+    }
+}
+
+// The persistent frame kernel.  Dynamic LDS: the largest unit layout of the
+// frame, then the draw bases (n + 1 words).
+__global__ __launch_bounds__(kFrameNT) void k_frame(const DrawDesc *draws, uint32_t n,
+                                                    const vr_shader_params *shaders, const uint32_t *unit_base,
+                                                    const uint32_t *slot_base, unsigned long long *agg,
+                                                    uint32_t unit_lds, uint32_t ballot_stride, uint32_t *err,
+                                                    unsigned long long *total_inv) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    uint32_t *s_base = (uint32_t *)(smem + unit_lds);
+    for (uint32_t d = threadIdx.x; d <= n; d += kFrameNT) s_base[d] = unit_base[d];
+    __syncthreads();
+    const uint32_t U = s_base[n];
+    const uint32_t G = gridDim.x;
+    for (uint32_t c0 = blockIdx.x * kFrameChunk; c0 < U; c0 += G * kFrameChunk) {
+        // the draw of unit c0: largest d with s_base[d] <= c0
+        uint32_t lo = 0, hi = n;   // invariant: s_base[lo] <= c0 < s_base[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (s_base[mid] <= c0) lo = mid;
+            else hi = mid;
+        }
+        uint32_t d = lo;
+        for (uint32_t u = c0; u < min(U, c0 + kFrameChunk); ++u) {
+            while (u >= s_base[d + 1]) ++d;   // units of empty draws are skipped
+            const DrawDesc D = draws[d];
+            const DrawArgs A = frame_args(D, agg + slot_base[d], err, total_inv);
+            const vr_shader_params &sh = shaders[D.shader];
+            const uint32_t nb = slot_base[d + 1] - slot_base[d];
+            const uint32_t local = u - s_base[d];
+            if (D.kind == 0) frame_unit_kind<0>(D, A, sh, local, nb, smem, ballot_stride);
+            else if (D.kind == 1) frame_unit_kind<1>(D, A, sh, local, nb, smem, ballot_stride);
+            else frame_unit_kind<2>(D, A, sh, local, nb, smem, ballot_stride);
+        }
+    }
+}
+
+// Per draw: counters = the sum of its aggregates; dtot[d] = its invocations.
+__global__ __launch_bounds__(64) void k_frame_finish(const DrawDesc *draws, const uint32_t *slot_base,
+                                                     const unsigned long long *agg, unsigned long long *dtot) {
+    const uint32_t d = blockIdx.x;
+    unsigned long long sum = 0;
+    for (uint32_t i = slot_base[d] + lane_id(); i < slot_base[d + 1]; i += kWave) sum += agg[i];
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) sum += __shfl_xor(sum, s, kWave);
+    if (lane_id() == 0) {
+        const unsigned long long inv = sum & 0xFFFFFFFFull, units = sum >> 32;
+        unsigned long long *c = draws[d].counters;
+        if (c) {
+            c[0] = inv;
+            c[1] = units;
+            c[2] = 0;
+            c[3] = 0;
+        }
+        dtot[d] = inv;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_frame_total(const unsigned long long *dtot, uint32_t n,
+                                                      unsigned long long *total_inv) {
+    __shared__ unsigned long long part[16];
+    unsigned long long sum = 0;
+    for (uint32_t d = threadIdx.x; d < n; d += 1024) sum += dtot[d];
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) sum += __shfl_xor(sum, s, kWave);
+    if (lane_id() == 0) part[threadIdx.x / kWave] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < 16; ++w) t += part[w];
+        *total_inv += t;
+    }
+}
+
+}  // namespace vr

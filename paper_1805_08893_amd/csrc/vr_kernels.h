@@ -89,8 +89,8 @@ __device__ __forceinline__ void shade_to_lds(const DrawArgs &A, const vr_shader_
 // stores float4 q of the span: fully coalesced 16-byte stores.
 template <int NT, typename LocalT>
 __device__ __forceinline__ void write_unit(const DrawArgs &A, uint32_t t0, uint32_t ntri, const LocalT *s_local,
-                                           const f4 *s_sv, uint32_t inv, uint32_t vbase, uint32_t unit) {
-    const uint32_t tid = threadIdx.x;
+                                           const f4 *s_sv, uint32_t inv, uint32_t vbase, uint32_t unit,
+                                           uint32_t tid) {
     const uint32_t ncorner = 3 * ntri;
     if (A.corners) {
         f4 *dst = A.corners + 9ull * t0;
@@ -156,12 +156,14 @@ __global__ __launch_bounds__(1024) void k_finish(const uint32_t *plan, uint32_t 
 // triangle); the block's corner rows are staged in LDS and stored
 // contiguously.
 // ---------------------------------------------------------------------------
+// One chunk of 256 corners (256 threads); s_sv holds 768 float4.  Returns
+// the chunk's aggregate ((triangles started) << 32 | invocations).
 template <int KIND>
-__global__ __launch_bounds__(256) void k_naive(DrawArgs A, vr_shader_params sh) {
-    __shared__ f4 s_sv[256 * 3];
+__device__ __forceinline__ unsigned long long naive_chunk(const DrawArgs &A, const vr_shader_params &sh,
+                                                          uint32_t chunk, f4 *s_sv) {
     const uint32_t tid = threadIdx.x;
     const uint64_t n = 3ull * A.T;
-    const uint64_t c0 = (uint64_t)blockIdx.x * 256;
+    const uint64_t c0 = (uint64_t)chunk * 256;
     const uint32_t cnt = (uint32_t)min<uint64_t>(256, n - c0);
     if (tid < cnt) {
         const uint64_t c = c0 + tid;
@@ -181,7 +183,17 @@ __global__ __launch_bounds__(256) void k_naive(DrawArgs A, vr_shader_params sh) 
         if (A.corners) __builtin_nontemporal_store(s_sv[q], A.corners + 3 * c0 + q);
         if (A.verts) __builtin_nontemporal_store(s_sv[q], A.verts + 3 * c0 + q);
     }
-    if (blockIdx.x == 0 && tid == 0) {
+    __syncthreads();
+    const uint64_t tris_started = (c0 + cnt + 2) / 3 - (c0 + 2) / 3;
+    return (tris_started << 32) | cnt;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_naive(DrawArgs A, vr_shader_params sh) {
+    __shared__ f4 s_sv[256 * 3];
+    naive_chunk<KIND>(A, sh, blockIdx.x, s_sv);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const unsigned long long n = 3ull * A.T;
         if (A.unit_offsets) A.unit_offsets[A.T] = A.T;
         if (A.counters) {
             A.counters[0] = n;
@@ -189,7 +201,7 @@ __global__ __launch_bounds__(256) void k_naive(DrawArgs A, vr_shader_params sh) 
             A.counters[2] = 0;
             A.counters[3] = 0;
         }
-        atomicAdd(A.total_inv, (unsigned long long)n);
+        atomicAdd(A.total_inv, n);
     }
 }
 
@@ -265,8 +277,8 @@ __device__ __forceinline__ uint32_t rank_flagged(uint32_t n, uint32_t *s_tmp, Fl
 //           key to a wavefront-cooperative probe of 64 slots at a time.
 // ---------------------------------------------------------------------------
 template <int NT, int MODE, int KIND>
-__global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+__device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_params &sh, uint32_t u, uint32_t nb,
+                                           unsigned char *smem) {
     const DedupLds L = dedup_lds_layout(MODE, A.max_idx, A.max_uniq, A.hash_bits);
     uint32_t *s_keys = (uint32_t *)(smem + L.keys);
     uint32_t *s_local = (uint32_t *)(smem + L.local);
@@ -276,9 +288,6 @@ __global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh) {
     __shared__ uint32_t s_vbase;
 
     const uint32_t tid = threadIdx.x, lane = lane_id();
-    const uint32_t nb = launch_units(A, batch_count(A));
-    const uint32_t u = blockIdx.x;
-    if (u >= nb) return;
     {
         uint32_t t0, t1;
         batch_range(A, u, t0, t1);
@@ -494,9 +503,18 @@ __global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh) {
             if (A.unit_offsets && u + 1 == nb) A.unit_offsets[nb] = A.T;
         }
         __syncthreads();
-        if (fits && (inv > 0 || n == 0)) write_unit<NT>(A, t0, t1 - t0, s_local, s_sv, inv, s_vbase, u);
-        if (tid == 0) A.agg[u] = (1ull << 32) | inv;
+        if (fits && (inv > 0 || n == 0)) write_unit<NT>(A, t0, t1 - t0, s_local, s_sv, inv, s_vbase, u, tid);
+        if (tid == 0 && A.agg) A.agg[u] = (1ull << 32) | inv;
+        __syncthreads();   // the caller may reuse the LDS for the next unit
     }
+}
+
+template <int NT, int MODE, int KIND>
+__global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const uint32_t nb = launch_units(A, batch_count(A));
+    if (blockIdx.x >= nb) return;
+    dedup_unit<NT, MODE, KIND>(A, sh, blockIdx.x, nb, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -565,55 +583,60 @@ __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t cur
     return cur;
 }
 
+// One batch processed by one wavefront; s_sv (64 x 3 float4) and s_map
+// (3 * batch_tris bytes) are private to the wavefront.  Only wavefront-level
+// synchronisation is used, so several wavefronts of a workgroup can work on
+// different batches.
+template <int KIND>
+__device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_params &sh, uint32_t b, uint32_t nb,
+                                             f4 *s_sv, uint8_t *s_map) {
+    const uint32_t lane = lane_id();
+    uint32_t t0, t1;
+    batch_range(A, b, t0, t1);
+    if (t1 < t0 || 3 * (t1 - t0) > A.max_idx) {   // only with a plan built for other limits
+        if (lane == 0) raise_error(A.err, VR_ERR_CAPACITY);
+        t1 = t0;
+    }
+    uint32_t vbase = 0, ubase = b;
+    RoundState st;
+    if (A.need_prefix) {
+        // counting sweep: the batch's rounds and invocations, published
+        // before any output so later batches can resolve their prefix
+        uint32_t rounds = 0, inv = 0;
+        for (uint32_t cur = t0; cur < t1; ++rounds) {
+            cur = ballot_round(A, cur, t1, nullptr, st);
+            inv += st.fill;
+        }
+        uint64_t ex = 0;
+        if (lane == 0) {
+            const uint64_t agg = ((uint64_t)rounds << 32) | inv;
+            lookback_publish(A.status, b, agg);
+            ex = lookback_resolve(A.status, b, agg, A.err);
+        }
+        vbase = __builtin_amdgcn_readfirstlane((uint32_t)ex);
+        ubase = __builtin_amdgcn_readfirstlane((uint32_t)((ex >> 32) & 0x3FFFFFFFu));
+    }
+    uint32_t r = 0, inv = 0;
+    for (uint32_t cur = t0; cur < t1; ++r) {
+        const uint32_t end = ballot_round(A, cur, t1, s_map, st);
+        if (lane < st.fill) shade_to_lds<KIND>(A, sh, st.my_id, s_sv + 3 * lane);
+        wave_sync_lds();
+        write_unit<64>(A, cur, end - cur, s_map, s_sv, st.fill, vbase, ubase + r, lane);
+        wave_sync_lds();
+        vbase += st.fill;
+        inv += st.fill;
+        cur = end;
+    }
+    if (A.unit_offsets && b + 1 == nb && lane == 0) A.unit_offsets[ubase + r] = A.T;
+    if (lane == 0 && A.agg) A.agg[b] = ((unsigned long long)r << 32) | inv;
+}
+
 template <int KIND>
 __global__ __launch_bounds__(64) void k_ballot(DrawArgs A, vr_shader_params sh) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    f4 *s_sv = (f4 *)smem;                    // 64 shaded vertices
-    uint8_t *s_map = smem + 64 * 48;          // local id per corner of a round
-    const uint32_t lane = lane_id();
     const uint32_t nb = launch_units(A, batch_count(A));
-    const uint32_t b = blockIdx.x;
-    if (b >= nb) return;
-    {
-        uint32_t t0, t1;
-        batch_range(A, b, t0, t1);
-        if (t1 < t0 || 3 * (t1 - t0) > A.max_idx) {   // only with a plan built for other limits
-            if (lane == 0) raise_error(A.err, VR_ERR_CAPACITY);
-            t1 = t0;
-        }
-        uint32_t vbase = 0, ubase = b;
-        RoundState st;
-        if (A.need_prefix) {
-            // counting sweep: the batch's rounds and invocations, published
-            // before any output so later batches can resolve their prefix
-            uint32_t rounds = 0, inv = 0;
-            for (uint32_t cur = t0; cur < t1; ++rounds) {
-                cur = ballot_round(A, cur, t1, nullptr, st);
-                inv += st.fill;
-            }
-            uint64_t ex = 0;
-            if (lane == 0) {
-                const uint64_t agg = ((uint64_t)rounds << 32) | inv;
-                lookback_publish(A.status, b, agg);
-                ex = lookback_resolve(A.status, b, agg, A.err);
-            }
-            vbase = __builtin_amdgcn_readfirstlane((uint32_t)ex);
-            ubase = __builtin_amdgcn_readfirstlane((uint32_t)((ex >> 32) & 0x3FFFFFFFu));
-        }
-        uint32_t r = 0, inv = 0;
-        for (uint32_t cur = t0; cur < t1; ++r) {
-            const uint32_t end = ballot_round(A, cur, t1, s_map, st);
-            if (lane < st.fill) shade_to_lds<KIND>(A, sh, st.my_id, s_sv + 3 * lane);
-            __syncthreads();
-            write_unit<64>(A, cur, end - cur, s_map, s_sv, st.fill, vbase, ubase + r);
-            __syncthreads();
-            vbase += st.fill;
-            inv += st.fill;
-            cur = end;
-        }
-        if (A.unit_offsets && b + 1 == nb && lane == 0) A.unit_offsets[ubase + r] = A.T;
-        if (lane == 0) A.agg[b] = ((unsigned long long)r << 32) | inv;
-    }
+    if (blockIdx.x >= nb) return;
+    ballot_batch<KIND>(A, sh, blockIdx.x, nb, (f4 *)smem, smem + 64 * 48);
 }
 
 }  // namespace vr

@@ -13,6 +13,7 @@
 #include "vr.h"
 #include "vr_kernels.h"
 #include "vr_plan.h"
+#include "vr_frame.h"
 
 using namespace vr;
 
@@ -334,6 +335,51 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
 
 }  // namespace
 
+struct vr_frame {
+    vr_ctx *c = nullptr;
+    uint32_t n = 0;
+    void *mem = nullptr;
+    DrawDesc *d_draws = nullptr;
+    vr_shader_params *d_shaders = nullptr;
+    uint32_t *d_unit_base = nullptr, *d_slot_base = nullptr;
+    unsigned long long *d_agg = nullptr, *d_dtot = nullptr;
+    uint32_t unit_lds = 0, ballot_stride = 0, lds_total = 0, grid = 1;
+    bool index_error = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void frame_enqueue(vr_frame *f, hipStream_t s) {
+    if (f->n == 0) return;
+    vr_ctx *c = f->c;
+    hipLaunchKernelGGL(k_frame_prepare, dim3(1), dim3(1024), 0, s, (const DrawDesc *)f->d_draws, f->n, f->d_unit_base,
+                       f->d_slot_base);
+    hipLaunchKernelGGL(k_frame, dim3(f->grid), dim3(kFrameNT), f->lds_total, s, (const DrawDesc *)f->d_draws, f->n,
+                       (const vr_shader_params *)f->d_shaders, (const uint32_t *)f->d_unit_base,
+                       (const uint32_t *)f->d_slot_base, f->d_agg, f->unit_lds, f->ballot_stride, &c->d_words->err,
+                       &c->d_words->total_inv);
+    hipLaunchKernelGGL(k_frame_finish, dim3(f->n), dim3(64), 0, s, (const DrawDesc *)f->d_draws,
+                       (const uint32_t *)f->d_slot_base, (const unsigned long long *)f->d_agg, f->d_dtot);
+    hipLaunchKernelGGL(k_frame_total, dim3(1), dim3(1024), 0, s, (const unsigned long long *)f->d_dtot, f->n,
+                       &c->d_words->total_inv);
+}
+
+uint32_t frame_mode(vr_strategy s) {
+    switch (s) {
+    case VR_NAIVE: return kFrameNaive;
+    case VR_STATIC_BALLOT:
+    case VR_DYN_BALLOT: return kFrameBallot;
+    case VR_STATIC_SORT:
+    case VR_DYN_SORT: return kFrameSort;
+    case VR_DYN_PHASH: return kFramePHash;
+    default: return kFrameHash;
+    }
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -533,6 +579,151 @@ vr_status vr_sync(vr_ctx *c, uint64_t *h_invocations) {
     if (e == VR_ERR_INDEX_RANGE) return fail(c, VR_ERR_INDEX_RANGE, "an index is >= num_vertices");
     if (e != 0) return fail(c, (vr_status)e, "device-side error %u", e);
     return VR_OK;
+}
+
+vr_status vr_frame_create(vr_ctx *c, const vr_draw *draws, uint32_t n, const vr_shader_params *shaders,
+                          uint32_t ns, int capture_graph, vr_frame **out) {
+    if (!c || !out) return VR_ERR_ARG;
+    *out = nullptr;
+    if (n > VR_MAX_FRAME_DRAWS) return fail(c, VR_ERR_ARG, "a frame holds at most %d draws", VR_MAX_FRAME_DRAWS);
+    if (n && (!draws || !shaders || ns == 0)) return fail(c, VR_ERR_ARG, "draws and shaders must not be NULL");
+    std::vector<DrawDesc> desc(n);
+    uint64_t slots = 0;
+    uint32_t unit_lds = 256 * 48, ballot_stride = 0;
+    bool index_error = false;
+    for (uint32_t d = 0; d < n; ++d) {
+        const vr_draw &D = draws[d];
+        if (D.shader >= ns) return fail(c, VR_ERR_ARG, "draw %u: shader %u out of range", d, D.shader);
+        vr_opts o{};
+        o.max_unique = D.max_unique;
+        o.d_plan = D.d_plan;
+        vr_outputs ov{};
+        ov.corners = D.d_corners;
+        ov.counters = D.d_counters;
+        Resolved r;
+        vr_status st = check_args(c, D.num_indices, &shaders[D.shader], D.strategy, D.batch_tris, &o, &ov, &r);
+        if (st != VR_OK) return fail(c, st, "draw %u: %s", d, c->error.c_str());
+        const uint64_t T = D.num_indices / 3;
+        if (T && (!D.d_indices || !D.d_vertices || !D.d_corners))
+            return fail(c, VR_ERR_ARG, "draw %u: indices, vertices and corners are required", d);
+        if (((uintptr_t)D.d_vertices & 15) || ((uintptr_t)D.d_corners & 15))
+            return fail(c, VR_ERR_ARG, "draw %u: vertices and corners must be 16-byte aligned", d);
+        if (is_dynamic(D.strategy) && T && !D.d_plan)
+            return fail(c, VR_ERR_ARG, "draw %u: a dynamic draw in a frame needs its plan", d);
+        if (T && D.num_vertices == 0) index_error = true;
+        DrawDesc &X = desc[d];
+        X.idx = D.d_indices;
+        X.vtx = (const f4 *)D.d_vertices;
+        X.corners = (f4 *)D.d_corners;
+        X.counters = (unsigned long long *)D.d_counters;
+        X.plan = is_dynamic(D.strategy) ? D.d_plan : nullptr;
+        X.V = D.num_vertices;
+        X.T = (T && D.num_vertices == 0) ? 0u : (uint32_t)T;
+        X.batch_tris = D.batch_tris;
+        X.num_batches = is_dynamic(D.strategy) ? 0u : (uint32_t)((T + D.batch_tris - 1) / D.batch_tris);
+        X.shader = D.shader;
+        X.mode = frame_mode(D.strategy);
+        X.kind = shaders[D.shader].kind;
+        X.max_idx = r.max_idx;
+        X.max_uniq = r.max_uniq;
+        X.hash_bits = r.hash_bits;
+        X.probes = r.probes;
+        if (X.mode == kFrameNaive) {
+            slots += (3 * T + 255) / 256;
+        } else {
+            slots += is_dynamic(D.strategy) ? dyn_batch_bound(T, r.nu, D.batch_tris) : X.num_batches;
+            if (X.mode == kFrameBallot) {
+                ballot_stride = std::max(ballot_stride, align16(64 * 48 + 3 * D.batch_tris));
+            } else {
+                unit_lds = std::max(unit_lds, dedup_lds_layout((int)X.mode, r.max_idx, r.max_uniq, r.hash_bits).total);
+            }
+        }
+    }
+    unit_lds = align16(std::max(unit_lds, 4 * ballot_stride));
+    const uint32_t lds_total = unit_lds + 4 * (n + 1);
+    if (lds_total > c->lds_limit)
+        return fail(c, VR_ERR_ARG, "frame needs %u B of LDS per workgroup (limit %zu)", lds_total, c->lds_limit);
+
+    DeviceGuard g(c->device);
+    vr_frame *f = new vr_frame();
+    f->c = c;
+    f->n = n;
+    f->unit_lds = unit_lds;
+    f->ballot_stride = ballot_stride;
+    f->lds_total = lds_total;
+    f->index_error = index_error;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_draws = 0, o_sh = al(sizeof(DrawDesc) * n), o_ub = o_sh + al(sizeof(vr_shader_params) * ns),
+                 o_sb = o_ub + al(4ull * (n + 1)), o_agg = o_sb + al(4ull * (n + 1)), o_dt = o_agg + al(8 * (slots + 1)),
+                 total = o_dt + al(8ull * (n + 1));
+    if (hipMalloc(&f->mem, total) != hipSuccess) {
+        delete f;
+        return fail(c, VR_ERR_OOM, "frame allocation of %zu bytes failed", total);
+    }
+    unsigned char *m = (unsigned char *)f->mem;
+    f->d_draws = (DrawDesc *)(m + o_draws);
+    f->d_shaders = (vr_shader_params *)(m + o_sh);
+    f->d_unit_base = (uint32_t *)(m + o_ub);
+    f->d_slot_base = (uint32_t *)(m + o_sb);
+    f->d_agg = (unsigned long long *)(m + o_agg);
+    f->d_dtot = (unsigned long long *)(m + o_dt);
+    hipError_t e = hipSuccess;
+    if (n) e = hipMemcpy(f->d_draws, desc.data(), sizeof(DrawDesc) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess && n) e = hipMemcpy(f->d_shaders, shaders, sizeof(vr_shader_params) * ns, hipMemcpyHostToDevice);
+    int per_cu = 0;
+    if (e == hipSuccess &&
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_frame, kFrameNT, lds_total) != hipSuccess || per_cu < 1))
+        per_cu = 1;
+    f->grid = (uint32_t)std::max(1, c->num_cus * per_cu);
+    if (e == hipSuccess && capture_graph && n) {
+        hipStream_t cs = nullptr;
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            frame_enqueue(f, cs);
+            e = hipStreamEndCapture(cs, &f->graph);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&f->exec, f->graph, nullptr, nullptr, 0);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+    if (e != hipSuccess) {
+        vr_frame_destroy(f);
+        return fail(c, VR_ERR_DEVICE, "frame setup: %s", hipGetErrorString(e));
+    }
+    *out = f;
+    return VR_OK;
+}
+
+vr_status vr_frame_run(vr_frame *f) {
+    if (!f) return VR_ERR_ARG;
+    vr_ctx *c = f->c;
+    DeviceGuard g(c->device);
+    if (f->index_error && !c->host_err) c->host_err = VR_ERR_INDEX_RANGE;
+    TimedRegion timed(c);
+    if (f->exec) VR_HIP(c, hipGraphLaunch(f->exec, c->stream));
+    else frame_enqueue(f, c->stream);
+    timed.done();
+    VR_HIP(c, hipGetLastError());
+    return VR_OK;
+}
+
+void vr_frame_destroy(vr_frame *f) {
+    if (!f) return;
+    DeviceGuard g(f->c->device);
+    (void)hipStreamSynchronize(f->c->stream);
+    if (f->exec) (void)hipGraphExecDestroy(f->exec);
+    if (f->graph) (void)hipGraphDestroy(f->graph);
+    if (f->mem) (void)hipFree(f->mem);
+    delete f;
+}
+
+vr_status vr_process_draws(vr_ctx *c, const vr_draw *draws, uint32_t n, const vr_shader_params *shaders, uint32_t ns) {
+    vr_frame *f = nullptr;
+    vr_status st = vr_frame_create(c, draws, n, shaders, ns, 0, &f);
+    if (st != VR_OK) return st;
+    st = vr_frame_run(f);
+    vr_frame_destroy(f);
+    return st;
 }
 
 vr_status vr_set_kernel_timing(vr_ctx *c, int enable) {

@@ -27,7 +27,8 @@ DYNAMIC = (VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH, VR_DYN_BALLOT)
 OUT_FLOATS = 12
 
 EXPORTS = ["vr_create", "vr_destroy", "vr_set_stream", "vr_check_args", "vr_plan_dynamic", "vr_process_draw",
-           "vr_sync", "vr_set_kernel_timing", "vr_kernel_times", "vr_last_error"]
+           "vr_sync", "vr_frame_create", "vr_frame_run", "vr_frame_destroy", "vr_process_draws",
+           "vr_set_kernel_timing", "vr_kernel_times", "vr_last_error"]
 
 
 class vr_opts(C.Structure):
@@ -47,6 +48,13 @@ class vr_outputs(C.Structure):
     _fields_ = [("corners", C.c_void_p), ("tris", C.c_void_p), ("verts", C.c_void_p),
                 ("verts_cap", C.c_uint64), ("local_idx", C.c_void_p), ("unit_offsets", C.c_void_p),
                 ("unit_invocations", C.c_void_p), ("units_cap", C.c_uint64), ("counters", C.c_void_p)]
+
+
+class vr_draw(C.Structure):
+    _fields_ = [("d_indices", C.c_void_p), ("num_indices", C.c_uint64), ("d_vertices", C.c_void_p),
+                ("num_vertices", C.c_uint32), ("shader", C.c_uint32), ("strategy", C.c_int),
+                ("batch_tris", C.c_uint32), ("max_unique", C.c_uint32), ("d_plan", C.c_void_p),
+                ("d_corners", C.c_void_p), ("d_counters", C.c_void_p)]
 
 
 class VrError(RuntimeError):
@@ -83,6 +91,15 @@ def lib():
         L.vr_process_draw.restype = C.c_int
         L.vr_sync.argtypes = [P, C.POINTER(C.c_uint64)]
         L.vr_sync.restype = C.c_int
+        L.vr_frame_create.argtypes = [P, C.POINTER(vr_draw), C.c_uint32, C.POINTER(vr_shader_params), C.c_uint32,
+                                      C.c_int, C.POINTER(C.c_void_p)]
+        L.vr_frame_create.restype = C.c_int
+        L.vr_frame_run.argtypes = [P]
+        L.vr_frame_run.restype = C.c_int
+        L.vr_frame_destroy.argtypes = [P]
+        L.vr_frame_destroy.restype = None
+        L.vr_process_draws.argtypes = [P, C.POINTER(vr_draw), C.c_uint32, C.POINTER(vr_shader_params), C.c_uint32]
+        L.vr_process_draws.restype = C.c_int
         L.vr_set_kernel_timing.argtypes = [P, C.c_int]
         L.vr_set_kernel_timing.restype = C.c_int
         L.vr_kernel_times.argtypes = [P, C.POINTER(C.c_float), C.c_uint32, C.POINTER(C.c_uint32)]
@@ -169,6 +186,43 @@ def vr_sync(ctx):
     inv = C.c_uint64(0)
     st = lib().vr_sync(ctx, C.byref(inv))
     return st, int(inv.value)
+
+
+def make_draw(indices, vertices, shader_index, strategy, batch_tris, corners, counters=None, max_unique=0,
+              plan=None) -> vr_draw:
+    """A frame entry from torch tensors (device memory)."""
+    V = vertices.shape[0] if vertices.dim() == 2 else vertices.numel() // 8
+    return vr_draw(indices.data_ptr() if indices.numel() else None, indices.numel(),
+                   vertices.data_ptr(), V, shader_index, strategy, batch_tris, max_unique,
+                   None if plan is None else plan.data_ptr(), corners.data_ptr() if corners.numel() else None,
+                   None if counters is None else counters.data_ptr())
+
+
+def _tables(draws, shaders):
+    dr = (vr_draw * max(1, len(draws)))(*draws)
+    sh = [x if isinstance(x, vr_shader_params) else make_shader(x) for x in shaders]
+    st = (vr_shader_params * max(1, len(sh)))(*sh)
+    return dr, st
+
+
+def vr_frame_create(ctx, draws, shaders, capture_graph=False):
+    dr, st = _tables(draws, shaders)
+    h = C.c_void_p()
+    rc = lib().vr_frame_create(ctx, dr, len(draws), st, len(shaders), 1 if capture_graph else 0, C.byref(h))
+    return rc, h
+
+
+def vr_frame_run(frame):
+    return lib().vr_frame_run(frame)
+
+
+def vr_frame_destroy(frame):
+    lib().vr_frame_destroy(frame)
+
+
+def vr_process_draws(ctx, draws, shaders):
+    dr, st = _tables(draws, shaders)
+    return lib().vr_process_draws(ctx, dr, len(draws), st, len(shaders))
 
 
 def vr_set_kernel_timing(ctx, enable):
