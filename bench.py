@@ -74,6 +74,96 @@ def committed_traffic(kernel):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+def scene_benchmark(stage, seed=3, num_draws=2000, replays=10):
+    """Many draws in one persistent launch (a hipGraph frame) against one
+    launch per draw, with autotuned per-class configurations.  Draw sizes are
+    log-normal in [100, 200000] triangles (mean about 5,000), each draw the
+    first T_d triangles of a grid or icosphere base mesh in Hilbert or scan
+    order, shaders MVP, Phong-4 or Phong-16."""
+    import torch
+    from paper_1805_08893_amd import vr
+    from paper_1805_08893_amd import workloads as W
+    from paper_1805_08893_amd.autotune import Autotuner
+
+    bases = [W.grid_mesh(318, 318, seed, "hilbert"), W.grid_mesh(318, 318, seed, "scan"),
+             W.icosphere_mesh(7, seed, "hilbert"), W.icosphere_mesh(7, seed, "scan")]
+    dev = [(torch.from_numpy(m.indices.view(np.int32)).cuda(), torch.from_numpy(m.vertices).cuda()) for m in bases]
+    shaders = [W.shader_for_mesh(bases[2], W.SHADER_MVP, seed),
+               W.shader_for_mesh(bases[2], W.SHADER_PHONG, seed, num_lights=4),
+               W.shader_for_mesh(bases[2], W.SHADER_PHONG, seed, num_lights=16)]
+    rng = np.random.default_rng(seed)
+    Ts = np.clip(np.exp(rng.normal(np.log(5000.0) - 0.72, 1.2, num_draws)), 100, 200000).astype(np.int64)
+    which = rng.integers(0, len(bases), num_draws)
+    shade = rng.integers(0, len(shaders), num_draws)
+    tuner = Autotuner(stage.ctx)
+    total_T = int(Ts.sum())
+    corners = torch.empty((3 * total_T, 12), dtype=torch.float32, device="cuda")
+    counters = torch.zeros((num_draws, 4), dtype=torch.int64, device="cuda")
+    draws, cfgs, plans = [], [], []
+    off = 0
+    t_tune = time.perf_counter()
+    for d in range(num_draws):
+        m = bases[which[d]]
+        T = int(min(Ts[d], m.num_tris))
+        idx, vtx = dev[which[d]][0][:3 * T], dev[which[d]][1]
+        key, (s, bt, nu) = tuner.choose(idx, m.indices[:3 * T], vtx, shaders[shade[d]])
+        plan = None
+        if s in vr.DYNAMIC:
+            plan = torch.empty(T + 2, dtype=torch.int32, device="cuda")
+            stage.check(vr.vr_plan_dynamic(stage.ctx, idx, m.num_verts, nu, bt, plan))
+        c = corners[3 * off:3 * (off + T)]
+        draws.append(vr.make_draw(idx, vtx, int(shade[d]), s, bt, c, counters[d], nu, plan))
+        cfgs.append((idx, vtx, int(shade[d]), s, bt, nu, plan, c, counters[d]))
+        plans.append(plan)
+        off += T
+    stage.check(stage.sync()[0])
+    t_tune = time.perf_counter() - t_tune
+    # one launch per draw
+    sh = [vr.make_shader(x) for x in shaders]
+    outs = [vr.vr_outputs(c.data_ptr(), None, None, 0, None, None, None, 0, cnt.data_ptr())
+            for (_, _, _, _, _, _, _, c, cnt) in cfgs]
+    opts = [vr.make_opts(max_unique=nu, plan=plan) for (_, _, _, _, _, nu, plan, _, _) in cfgs]
+
+    def per_draw():
+        for k, (idx, vtx, si, s, bt, nu, plan, c, cnt) in enumerate(cfgs):
+            stage.check(vr.vr_process_draw(stage.ctx, idx, vtx, sh[si], s, bt, opts[k], outs[k]))
+
+    per_draw()
+    stage.check(stage.sync()[0])
+    inv_loop = int(counters[:, 0].sum().item())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        per_draw()
+    e1.record()
+    torch.cuda.synchronize()
+    loop_ms = e0.elapsed_time(e1) / 3
+    stage.check(stage.sync()[0])
+    rc, frame = vr.vr_frame_create(stage.ctx, draws, shaders, capture_graph=True)
+    stage.check(rc)
+    try:
+        counters.zero_()
+        for _ in range(2):
+            stage.check(vr.vr_frame_run(frame))
+        stage.check(stage.sync()[0])
+        inv_frame = int(counters[:, 0].sum().item())
+        e0.record()
+        for _ in range(replays):
+            stage.check(vr.vr_frame_run(frame))
+        e1.record()
+        torch.cuda.synchronize()
+        frame_ms = e0.elapsed_time(e1) / replays
+        stage.check(stage.sync()[0])
+    finally:
+        vr.vr_frame_destroy(frame)
+    classes = {k: {"strategy": vr.STRATEGY_NAMES[v["strategy"]], "batch_tris": v["batch_tris"],
+                   "max_unique": v["max_unique"]} for k, v in tuner.table.items()}
+    return {"draws": num_draws, "triangles": total_T, "frame_ms": frame_ms, "per_draw_launch_ms": loop_ms,
+            "frame_tri_per_s": total_T / (frame_ms * 1e-3), "per_draw_tri_per_s": total_T / (loop_ms * 1e-3),
+            "speedup_frame_vs_per_draw": loop_ms / frame_ms, "invocations_frame": inv_frame,
+            "invocations_per_draw": inv_loop, "autotune_and_plan_s": t_tune, "classes": classes}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +173,7 @@ def main():
     ap.add_argument("--cpu-passes", type=int, default=1)
     ap.add_argument("--level", type=int, default=8, help="icosphere subdivision level")
     ap.add_argument("--only", default=None, help="run only this strategy in each step (profiling)")
+    ap.add_argument("--no-scene", action="store_true", help="skip the many-draw frame measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="time a plain device-to-device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -222,6 +313,13 @@ def main():
                "sample": f"{args.cpu_passes} pass(es) of the full step (5 strategies x {T} triangles), "
                          f"single-threaded C oracle, {t_cpu:.1f} s"}
 
+    scene = None
+    if not args.no_scene and not args.only:
+        try:
+            scene = scene_benchmark(stage)
+        except Exception as exc:   # the headline line must still be printed
+            scene = {"error": repr(exc)}
+
     line = {"metric": METRIC, "value": value, "unit": "triangles/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -229,7 +327,7 @@ def main():
                        "unique_vertices": U, "strategies": [s[0] for s in strategies],
                        "static_batch_tris": 64, "dynamic_max_unique": NU, "dynamic_max_tris": NP,
                        "output": "per-corner shaded vertices + invocation counters"},
-            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per}
+            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "scene": scene}
     print(json.dumps(line), flush=True)
     stage.close()
 

@@ -240,6 +240,30 @@ vr_status vr_process_draws(vr_ctx *ctx, const vr_draw *draws, uint32_t num_draws
                            uint32_t num_shaders);
 
 /*
+ * Autotuning support: time candidate configurations on a sample draw (the
+ * paper picks its batch sizes by such a search, Sections 4.2 and 5).  For
+ * every candidate the draw is processed with per-corner output into context
+ * scratch: the plan is built (timed as plan_ms) for dynamic strategies, one
+ * untimed warm-up, then `reps` timed draws (kernel_ms = mean time of the main
+ * kernel).  Invalid candidates get kernel_ms = -1.  *best receives the index
+ * of the fastest valid candidate by kernel_ms.  Synchronous; allocates
+ * scratch as needed.
+ */
+typedef struct {
+    vr_strategy strategy;
+    uint32_t batch_tris;
+    uint32_t max_unique;      /* DYN_*: 0 = default                            */
+    uint32_t wg_size;         /* 0 = automatic                                 */
+    float kernel_ms;          /* out                                           */
+    float plan_ms;            /* out: dynamic strategies, else 0               */
+    uint64_t invocations;     /* out                                           */
+} vr_tune_candidate;
+
+vr_status vr_autotune(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_indices, const float *d_vertices,
+                      uint32_t num_vertices, const vr_shader_params *shader, vr_tune_candidate *cands,
+                      uint32_t num_cands, uint32_t reps, uint32_t *best);
+
+/*
  * Kernel timing (a measurement aid, off by default).  While enabled, every
  * vr_process_draw records a pair of HIP events on the context's stream
  * around its main kernel, every vr_plan_dynamic around its kernels and every

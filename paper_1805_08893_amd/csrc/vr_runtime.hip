@@ -43,7 +43,7 @@ struct vr_ctx {
     size_t lds_limit = 65536;
     std::string error;
     CtxWords *d_words = nullptr;
-    Scratch status, agg, plan, plan_work;
+    Scratch status, agg, plan, plan_work, tune;
     uint32_t host_err = 0;   // data error found on the host, reported by vr_sync
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;   // reused event pairs
@@ -414,7 +414,7 @@ void vr_destroy(vr_ctx *c) {
     if (!c) return;
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (Scratch *s : {&c->status, &c->agg, &c->plan, &c->plan_work})
+    for (Scratch *s : {&c->status, &c->agg, &c->plan, &c->plan_work, &c->tune})
         if (s->ptr) (void)hipFree(s->ptr);
     for (auto &pr : c->ev_pool) {
         (void)hipEventDestroy(pr.first);
@@ -724,6 +724,92 @@ vr_status vr_process_draws(vr_ctx *c, const vr_draw *draws, uint32_t n, const vr
     st = vr_frame_run(f);
     vr_frame_destroy(f);
     return st;
+}
+
+vr_status vr_autotune(vr_ctx *c, const uint32_t *d_idx, uint64_t num_indices, const float *d_vtx, uint32_t V,
+                      const vr_shader_params *sh, vr_tune_candidate *cands, uint32_t ncand, uint32_t reps,
+                      uint32_t *best) {
+    if (!c || !sh || (ncand && !cands)) return VR_ERR_ARG;
+    if (num_indices % 3 != 0 || num_indices > VR_MAX_INDICES) return fail(c, VR_ERR_ARG, "bad num_indices");
+    const uint64_t T = num_indices / 3;
+    if (reps == 0) reps = 1;
+    DeviceGuard g(c->device);
+    // scratch: corners, plan, counters
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_plan = al(48ull * 3 * T), o_cnt = o_plan + al(4ull * (T + 2)), total = o_cnt + 256;
+    vr_status st = ensure(c, c->tune, total);
+    if (st != VR_OK) return st;
+    unsigned char *m = (unsigned char *)c->tune.ptr;
+    float *corners = (float *)m;
+    uint32_t *plan = (uint32_t *)(m + o_plan);
+    uint64_t *counters = (uint64_t *)(m + o_cnt);
+    // the search's invocations and errors are its own: keep the caller's
+    VR_HIP(c, hipStreamSynchronize(c->stream));
+    CtxWords saved{};
+    VR_HIP(c, hipMemcpy(&saved, c->d_words, sizeof saved, hipMemcpyDeviceToHost));
+    VR_HIP(c, hipMemset(c->d_words, 0, sizeof saved));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    VR_HIP(c, hipEventCreate(&e0));
+    VR_HIP(c, hipEventCreate(&e1));
+    const bool was_timing = c->timing;
+    c->timing = false;
+    float best_ms = -1.0f;
+    uint32_t best_i = 0;
+    for (uint32_t i = 0; i < ncand; ++i) {
+        vr_tune_candidate &k = cands[i];
+        k.kernel_ms = -1.0f;
+        k.plan_ms = 0.0f;
+        k.invocations = 0;
+        vr_opts o{};
+        o.max_unique = k.max_unique;
+        o.wg_size = k.wg_size;
+        vr_outputs out{};
+        out.corners = corners;
+        out.counters = counters;
+        Resolved r;
+        if (check_args(c, num_indices, sh, k.strategy, k.batch_tris, &o, &out, &r) != VR_OK) continue;
+        if (is_dynamic(k.strategy)) {
+            (void)hipEventRecord(e0, c->stream);
+            if (vr_plan_dynamic(c, d_idx, num_indices, V, r.nu, k.batch_tris, plan, T + 2) != VR_OK) continue;
+            (void)hipEventRecord(e1, c->stream);
+            VR_HIP(c, hipEventSynchronize(e1));
+            VR_HIP(c, hipEventElapsedTime(&k.plan_ms, e0, e1));
+            o.d_plan = plan;
+        }
+        if (vr_process_draw(c, d_idx, num_indices, d_vtx, V, sh, k.strategy, k.batch_tris, &o, &out) != VR_OK) continue;
+        c->timing = true;
+        const size_t first = c->ev_used;
+        bool ok = true;
+        for (uint32_t rep = 0; rep < reps && ok; ++rep)
+            ok = vr_process_draw(c, d_idx, num_indices, d_vtx, V, sh, k.strategy, k.batch_tris, &o, &out) == VR_OK;
+        c->timing = false;
+        VR_HIP(c, hipStreamSynchronize(c->stream));
+        float sum = 0.0f;
+        for (size_t j = first; j < c->ev_used; ++j) {
+            float ms = 0.0f;
+            VR_HIP(c, hipEventElapsedTime(&ms, c->ev_pool[j].first, c->ev_pool[j].second));
+            sum += ms;
+        }
+        const size_t timed = c->ev_used - first;
+        c->ev_used = first;
+        if (!ok || timed == 0) continue;
+        VR_HIP(c, hipMemcpy(&k.invocations, counters, sizeof(uint64_t), hipMemcpyDeviceToHost));
+        k.kernel_ms = sum / (float)timed;
+        if (best_ms < 0.0f || k.kernel_ms < best_ms) {
+            best_ms = k.kernel_ms;
+            best_i = i;
+        }
+    }
+    c->timing = was_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    VR_HIP(c, hipStreamSynchronize(c->stream));
+    CtxWords mine{};
+    VR_HIP(c, hipMemcpy(&mine, c->d_words, sizeof mine, hipMemcpyDeviceToHost));
+    VR_HIP(c, hipMemcpy(c->d_words, &saved, sizeof saved, hipMemcpyHostToDevice));
+    if (best) *best = best_i;
+    if (mine.err) return fail(c, (vr_status)mine.err, "device-side error %u during the search", mine.err);
+    return best_ms < 0.0f ? fail(c, VR_ERR_ARG, "no valid candidate") : VR_OK;
 }
 
 vr_status vr_set_kernel_timing(vr_ctx *c, int enable) {

@@ -27,7 +27,7 @@ DYNAMIC = (VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH, VR_DYN_BALLOT)
 OUT_FLOATS = 12
 
 EXPORTS = ["vr_create", "vr_destroy", "vr_set_stream", "vr_check_args", "vr_plan_dynamic", "vr_process_draw",
-           "vr_sync", "vr_frame_create", "vr_frame_run", "vr_frame_destroy", "vr_process_draws",
+           "vr_sync", "vr_frame_create", "vr_frame_run", "vr_frame_destroy", "vr_process_draws", "vr_autotune",
            "vr_set_kernel_timing", "vr_kernel_times", "vr_last_error"]
 
 
