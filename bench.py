@@ -164,6 +164,71 @@ def scene_benchmark(stage, seed=3, num_draws=2000, replays=10):
             "invocations_per_draw": inv_loop, "autotune_and_plan_s": t_tune, "classes": classes}
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def serving_benchmark(stage, seed=11, n=2000, rate=500.0, budget=64 << 30):
+    """A Poisson stream of draw requests against 200 resident meshes, served by
+    the continuous-batching server and by the same server launching every
+    request alone; plus a burst of the same requests for peak throughput."""
+    import torch
+    from paper_1805_08893_amd import vr, serve
+    from paper_1805_08893_amd import workloads as W
+    from paper_1805_08893_amd.autotune import Autotuner
+
+    bases = W.serving_bases(seed)
+    pool = W.serving_pool(bases, seed + 1)
+    tr = W.serving_trace(pool, seed + 2, n=n, rate=rate)
+    dev = [(torch.from_numpy(m.indices.view(np.int32)).cuda(), torch.from_numpy(m.vertices).cuda()) for m in bases]
+    shaders = {}
+    tuner = Autotuner(stage.ctx)
+    plan_of = []
+    for i in range(n):
+        b, start, _ = pool[tr["mesh"][i]]
+        L, size = int(tr["lights"][i]), int(tr["size"][i])
+        if (b, L) not in shaders:
+            sp = W.shader_for_mesh(bases[b], W.SHADER_PHONG, seed + b, num_lights=L)
+            shaders[(b, L)] = (sp, vr.make_shader(sp))
+        idx = dev[b][0][3 * start:3 * (start + size)]
+        host = bases[b].indices[3 * start:3 * (start + size)]
+        _, cfg = tuner.choose(idx, host, dev[b][1], shaders[(b, L)][0])
+        plan_of.append(cfg)
+    stage.check(stage.sync()[0])
+
+    def run(max_tick_draws):
+        with serve.Server(budget, max_inflight=2, max_tick_draws=max_tick_draws) as srv:
+            ids = [srv.add_mesh(dev[b][0][3 * start:], dev[b][1]) for b, start, _ in pool]
+            reqs = [vr.make_request(ids[tr["mesh"][i]], int(tr["size"][i]),
+                                    shaders[(pool[tr["mesh"][i]][0], int(tr["lights"][i]))][1],
+                                    plan_of[i][0], plan_of[i][1], plan_of[i][2], user=i) for i in range(n)]
+            for r in reqs:                      # warm-up: builds and caches every plan
+                srv.submit(r)
+            srv.drain(n)
+            t0 = time.perf_counter()
+            for r in reqs:                      # burst: everything at once
+                srv.submit(r)
+            got = srv.drain(n)
+            burst = serve.summarize(got, time.perf_counter() - t0)
+            got, late, wall = serve.replay(srv, reqs, tr["arrival"])
+            out = serve.summarize(got, wall)
+            out["submit_late_ms_p99"] = float(np.percentile(late, 99) * 1e3)
+            out["burst_tri_per_s"] = burst["tri_per_s"]
+            out["burst_wall_s"] = burst["wall_s"]
+            out["burst_requests_per_tick"] = burst["requests_per_tick"]
+            out["stats"] = {k: v for k, v in srv.stats().items()
+                            if k in ("ticks", "peak_reserved_bytes", "admission_blocked", "max_tick_draws", "plan_bytes")}
+            return out
+
+    progress("serving: configurations chosen")
+    batched = run(1024)
+    progress("serving: batched server done")
+    single = run(1)
+    progress("serving: per-request launches done")
+    return {"requests": n, "rate_req_per_s": rate, "mean_tris": float(tr["size"].mean()),
+            "meshes": len(pool), "budget_bytes": budget, "batched": batched, "per_request_launch": single}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +239,7 @@ def main():
     ap.add_argument("--level", type=int, default=8, help="icosphere subdivision level")
     ap.add_argument("--only", default=None, help="run only this strategy in each step (profiling)")
     ap.add_argument("--no-scene", action="store_true", help="skip the many-draw frame measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="time a plain device-to-device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -317,8 +383,15 @@ def main():
     if not args.no_scene and not args.only:
         try:
             scene = scene_benchmark(stage)
+            progress("scene done")
         except Exception as exc:   # the headline line must still be printed
             scene = {"error": repr(exc)}
+    serving = None
+    if not args.no_serve and not args.only:
+        try:
+            serving = serving_benchmark(stage)
+        except Exception as exc:
+            serving = {"error": repr(exc)}
 
     line = {"metric": METRIC, "value": value, "unit": "triangles/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -327,7 +400,7 @@ def main():
                        "unique_vertices": U, "strategies": [s[0] for s in strategies],
                        "static_batch_tris": 64, "dynamic_max_unique": NU, "dynamic_max_tris": NP,
                        "output": "per-corner shaded vertices + invocation counters"},
-            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "scene": scene}
+            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "scene": scene, "serving": serving}
     print(json.dumps(line), flush=True)
     stage.close()
 

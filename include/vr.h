@@ -48,7 +48,8 @@ typedef enum {
     VR_ERR_CAPACITY = 3,     /* an output capacity is below the documented bound */
     VR_ERR_OOM = 4,          /* device memory for the context's scratch failed  */
     VR_ERR_DEVICE = 5,       /* a HIP call failed, or a device-side wait ran out */
-    VR_ERR_BUSY = 6          /* reserved                                         */
+    VR_ERR_BUSY = 6,         /* the object is in a state that forbids the call   */
+    VR_CANCELLED = 7         /* (server) the request was cancelled before launch */
 } vr_status;
 
 /*
@@ -202,7 +203,11 @@ vr_status vr_sync(vr_ctx *ctx, uint64_t *h_invocations);
  * processed exactly as vr_process_draw would process it with only `corners`
  * and `counters` requested, so every draw keeps its own batches, ids and
  * invocation counts.  Dynamic draws need their plan (vr_plan_dynamic with the
- * same indices, max_unique and batch_tris) in d_plan.
+ * same indices, max_unique and batch_tris) in d_plan, or the plan of any
+ * longer index buffer that starts with this draw's indices: greedy batching
+ * never looks past the end of the batch it closes, so the plan of a prefix
+ * of the stream is the longer plan cut at the prefix's end (the last batch
+ * shortened to end there).
  */
 typedef struct vr_frame vr_frame;
 
@@ -275,6 +280,125 @@ vr_status vr_autotune(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_indic
  */
 vr_status vr_set_kernel_timing(vr_ctx *ctx, int enable);
 vr_status vr_kernel_times(vr_ctx *ctx, float *ms, uint32_t cap, uint32_t *count);
+
+/*
+ * Request server: continuous batching of draw requests against meshes that
+ * stay resident in device memory (the geometry stage of Section 4.2 fed by
+ * a stream of requests instead of one draw call).
+ *
+ * A server owns its own HIP stream, a device arena of `budget_bytes` for
+ * request outputs, and a scheduler thread.  vr_server_submit queues a
+ * request and returns at once.  The scheduler admits requests in submission
+ * order while their outputs (3T shaded corners, 144 bytes per triangle) fit
+ * in the arena, and launches "ticks": one frame launch over the admitted
+ * requests, at most max_tick_draws requests and max_tick_tris triangles,
+ * with at most max_inflight ticks queued on the device.  Requests that
+ * arrive while ticks run join the next tick.  Each request is processed
+ * exactly as vr_process_draw would process its draw (bit-identical corners
+ * and counts, alone or in any mix).  A finished request keeps its memory
+ * until vr_server_release.  With max_tick_draws = 1 every request gets its
+ * own launch (the per-draw baseline).
+ *
+ * Threading: submit, poll, release, cancel and stats may be called from any
+ * host thread; destroy from one thread after all others have stopped using
+ * the server.
+ */
+typedef struct vr_server vr_server;
+
+typedef struct {
+    uint64_t budget_bytes;    /* arena for request outputs, allocated at create */
+    uint32_t max_inflight;    /* ticks queued on the device at once, 1..8; 0 -> 2 */
+    uint32_t max_tick_draws;  /* requests per tick, 1..VR_MAX_FRAME_DRAWS; 0 -> 1024 */
+    uint64_t max_tick_tris;   /* triangles per tick; 0 = no limit (a tick always
+                                 takes at least one request)                    */
+} vr_server_config;
+
+typedef struct {
+    uint32_t mesh;            /* from vr_server_add_mesh                        */
+    uint32_t num_tris;        /* the first num_tris triangles of the mesh       */
+    vr_strategy strategy;
+    uint32_t batch_tris;      /* as for vr_process_draw                         */
+    uint32_t max_unique;      /* DYN_*: N_u, 0 = default                        */
+    uint32_t pad;
+    uint64_t user;            /* opaque, returned in the completion             */
+    vr_shader_params shader;  /* copied at submit                               */
+} vr_request;
+
+typedef struct {
+    uint64_t ticket, user;
+    int32_t status;           /* VR_OK, VR_CANCELLED, or the device error of its tick */
+    uint32_t tick;            /* tick that processed it                         */
+    uint64_t num_tris, invocations, units;
+    const float *d_corners;   /* float32[3 num_tris][12] in the arena; valid until
+                                 vr_server_release                              */
+    double t_submit, t_admit, t_launch, t_done;   /* seconds since create; t_done
+                                 is when the scheduler saw the tick finish     */
+} vr_completion;
+
+typedef struct {
+    uint64_t submitted, completed, cancelled, rejected, ticks;
+    uint64_t budget_bytes, reserved_bytes, peak_reserved_bytes;
+    uint64_t pending, admitted, inflight_ticks;
+    uint64_t max_pending, max_tick_draws, admission_blocked;
+    uint64_t plan_bytes;      /* cached dynamic plans (outside the budget)      */
+} vr_server_stats;
+
+/* Allocates the arena and starts the scheduler on `device`.  VR_ERR_ARG for
+ * out-of-range settings, VR_ERR_OOM if the arena cannot be allocated. */
+vr_status vr_server_create(int device, const vr_server_config *cfg, vr_server **server);
+/* Registers a resident mesh (caller-owned buffers that must outlive the
+ * server).  Synchronous: checks on the device that every index is below
+ * num_vertices (VR_ERR_INDEX_RANGE otherwise), so requests cannot fault.
+ * Dynamic plans of the whole mesh are built on first use for each
+ * (max_unique, batch_tris) and cached; a request on a prefix uses the cached
+ * plan cut at its end. */
+vr_status vr_server_add_mesh(vr_server *server, const uint32_t *d_indices, uint64_t num_indices,
+                             const float *d_vertices, uint32_t num_vertices, uint32_t *mesh);
+/* Queues a request.  VR_ERR_ARG for an unknown mesh, num_tris beyond the
+ * mesh, or any argument vr_process_draw would reject; VR_ERR_CAPACITY when
+ * its output can never fit in the budget; VR_ERR_BUSY after destroy began. */
+vr_status vr_server_submit(vr_server *server, const vr_request *request, uint64_t *ticket);
+/* Returns up to `cap` finished requests, oldest first, waiting up to
+ * timeout_ms for the first one (0 = do not wait). */
+vr_status vr_server_poll(vr_server *server, vr_completion *out, uint32_t cap, uint32_t *count, uint32_t timeout_ms);
+/* Frees a finished request's memory.  VR_ERR_BUSY if it has not finished,
+ * VR_ERR_ARG for an unknown ticket. */
+vr_status vr_server_release(vr_server *server, uint64_t ticket);
+/* Copies a finished request's corners (144 bytes per triangle) to host
+ * memory `dst` of `bytes` bytes (synchronous).  VR_ERR_BUSY if it has not
+ * finished, VR_ERR_CAPACITY if bytes is too small. */
+vr_status vr_server_fetch(vr_server *server, uint64_t ticket, void *dst, uint64_t bytes);
+/* Cancels a request that has not been launched (it completes with
+ * VR_CANCELLED); VR_ERR_BUSY once launched. */
+vr_status vr_server_cancel(vr_server *server, uint64_t ticket);
+vr_status vr_server_stats_get(vr_server *server, vr_server_stats *stats);
+/* Cancels what is not launched, waits for the device, frees everything. */
+void vr_server_destroy(vr_server *server);
+const char *vr_server_last_error(const vr_server *server);
+
+/*
+ * The server's admission and tick policy on a simulated clock (host only, no
+ * device): requests (sorted by arrival) reserve `bytes`, ticks run one after
+ * another on a simulated device taking tick_fixed_s + tick_s_per_tri x (their
+ * triangles), a finished request is released `hold` seconds after it
+ * finishes, and a request with cancel_at >= 0 is cancelled at that time if
+ * it has not been launched.
+ */
+typedef struct {
+    double arrival, cancel_at, hold;
+    uint64_t num_tris, bytes;
+} vr_sim_request;
+
+typedef struct {
+    int32_t status;
+    uint32_t tick;
+    double t_admit, t_launch, t_done, t_release;   /* -1 when it did not happen */
+    uint64_t offset;          /* arena offset while admitted                    */
+} vr_sim_result;
+
+vr_status vr_server_simulate(const vr_server_config *cfg, const vr_sim_request *requests, uint32_t num_requests,
+                             double tick_fixed_s, double tick_s_per_tri, vr_sim_result *results,
+                             vr_server_stats *stats);
 
 /* Text of the last error on ctx (or of the last vr_create failure when ctx
  * is NULL).  Valid until the next call on the same context. */

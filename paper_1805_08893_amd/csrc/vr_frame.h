@@ -33,13 +33,28 @@ struct DrawDesc {
     uint32_t max_idx, max_uniq, hash_bits, probes;
 };
 
+// Batches of a plan that start before triangle T.  A plan built for a
+// longer stream with the same start, cut at T, is the plan of the first T
+// triangles: greedy batching closes a batch without looking past it.
+__device__ __forceinline__ uint32_t plan_prefix_batches(const uint32_t *plan, uint32_t T) {
+    const uint32_t B = plan[0];
+    if (plan[1 + B] <= T) return B;
+    uint32_t lo = 0, hi = B;   // plan[1 + lo] < T <= plan[1 + hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (plan[1 + mid] < T) lo = mid;
+        else hi = mid;
+    }
+    return hi;
+}
+
 // Units (workgroup tasks) and aggregate slots of a draw.
 __device__ __forceinline__ void frame_draw_units(const DrawDesc &D, uint32_t &units, uint32_t &slots) {
     if (D.mode == kFrameNaive) {
         units = slots = (uint32_t)((3ull * D.T + 255) / 256);
         return;
     }
-    const uint32_t nb = D.T == 0 ? 0u : (D.plan ? D.plan[0] : D.num_batches);
+    const uint32_t nb = D.T == 0 ? 0u : (D.plan ? plan_prefix_batches(D.plan, D.T) : D.num_batches);
     slots = nb;
     units = D.mode == kFrameBallot ? (nb + 3) / 4 : nb;   // four wavefronts, four ballot batches
 }

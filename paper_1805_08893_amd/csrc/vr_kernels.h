@@ -53,9 +53,9 @@ __device__ __forceinline__ uint32_t batch_count(const DrawArgs &A) {
 }
 
 __device__ __forceinline__ void batch_range(const DrawArgs &A, uint32_t b, uint32_t &t0, uint32_t &t1) {
-    if (A.plan) {
+    if (A.plan) {   // the plan may be that of a longer stream with the same start
         t0 = A.plan[1 + b];
-        t1 = A.plan[2 + b];
+        t1 = min(A.plan[2 + b], A.T);
     } else {
         t0 = b * A.batch_tris;
         t1 = min(A.T, t0 + A.batch_tris);

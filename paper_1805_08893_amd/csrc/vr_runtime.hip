@@ -4,16 +4,24 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "vr.h"
 #include "vr_kernels.h"
 #include "vr_plan.h"
 #include "vr_frame.h"
+#include "vr_sched.h"
 
 using namespace vr;
 
@@ -351,19 +359,37 @@ struct vr_frame {
 
 namespace {
 
+// The frame kernels: unit bases, the persistent kernel, per-draw counters
+// and (when total_inv is not NULL) the frame's invocation total.
+struct FrameLaunch {
+    const DrawDesc *draws;
+    uint32_t n;
+    const vr_shader_params *shaders;
+    uint32_t *unit_base, *slot_base;
+    unsigned long long *agg, *dtot;
+    uint32_t unit_lds, ballot_stride, lds_total, grid;
+    uint32_t *err;
+    unsigned long long *total_inv;
+};
+
+void enqueue_frame_kernels(const FrameLaunch &L, hipStream_t s) {
+    if (L.n == 0) return;
+    hipLaunchKernelGGL(k_frame_prepare, dim3(1), dim3(1024), 0, s, L.draws, L.n, L.unit_base, L.slot_base);
+    hipLaunchKernelGGL(k_frame, dim3(L.grid), dim3(kFrameNT), L.lds_total, s, L.draws, L.n, L.shaders,
+                       (const uint32_t *)L.unit_base, (const uint32_t *)L.slot_base, L.agg, L.unit_lds,
+                       L.ballot_stride, L.err, L.total_inv);
+    hipLaunchKernelGGL(k_frame_finish, dim3(L.n), dim3(64), 0, s, L.draws, (const uint32_t *)L.slot_base,
+                       (const unsigned long long *)L.agg, L.dtot);
+    if (L.total_inv)
+        hipLaunchKernelGGL(k_frame_total, dim3(1), dim3(1024), 0, s, (const unsigned long long *)L.dtot, L.n,
+                           L.total_inv);
+}
+
 void frame_enqueue(vr_frame *f, hipStream_t s) {
-    if (f->n == 0) return;
     vr_ctx *c = f->c;
-    hipLaunchKernelGGL(k_frame_prepare, dim3(1), dim3(1024), 0, s, (const DrawDesc *)f->d_draws, f->n, f->d_unit_base,
-                       f->d_slot_base);
-    hipLaunchKernelGGL(k_frame, dim3(f->grid), dim3(kFrameNT), f->lds_total, s, (const DrawDesc *)f->d_draws, f->n,
-                       (const vr_shader_params *)f->d_shaders, (const uint32_t *)f->d_unit_base,
-                       (const uint32_t *)f->d_slot_base, f->d_agg, f->unit_lds, f->ballot_stride, &c->d_words->err,
-                       &c->d_words->total_inv);
-    hipLaunchKernelGGL(k_frame_finish, dim3(f->n), dim3(64), 0, s, (const DrawDesc *)f->d_draws,
-                       (const uint32_t *)f->d_slot_base, (const unsigned long long *)f->d_agg, f->d_dtot);
-    hipLaunchKernelGGL(k_frame_total, dim3(1), dim3(1024), 0, s, (const unsigned long long *)f->d_dtot, f->n,
-                       &c->d_words->total_inv);
+    FrameLaunch L{f->d_draws, f->n, f->d_shaders, f->d_unit_base, f->d_slot_base, f->d_agg, f->d_dtot,
+                  f->unit_lds, f->ballot_stride, f->lds_total, f->grid, &c->d_words->err, &c->d_words->total_inv};
+    enqueue_frame_kernels(L, s);
 }
 
 uint32_t frame_mode(vr_strategy s) {
@@ -376,6 +402,70 @@ uint32_t frame_mode(vr_strategy s) {
     case VR_DYN_PHASH: return kFramePHash;
     default: return kFrameHash;
     }
+}
+
+// Per-frame LDS and aggregate needs, accumulated over its draws.
+struct FrameNeeds {
+    uint64_t slots = 0, units = 0;
+    uint32_t unit_lds = 256 * 48, ballot_stride = 0;
+    bool index_error = false;
+    uint32_t lds_total(uint32_t n) const {
+        return align16(std::max(unit_lds, 4 * ballot_stride)) + 4 * (n + 1);
+    }
+};
+
+// Validates one frame entry and fills its device descriptor.
+vr_status describe_draw(vr_ctx *c, const vr_draw &D, const vr_shader_params &sh, uint32_t d, DrawDesc &X,
+                        FrameNeeds &need) {
+    vr_opts o{};
+    o.max_unique = D.max_unique;
+    o.d_plan = D.d_plan;
+    vr_outputs ov{};
+    ov.corners = D.d_corners;
+    ov.counters = D.d_counters;
+    Resolved r;
+    vr_status st = check_args(c, D.num_indices, &sh, D.strategy, D.batch_tris, &o, &ov, &r);
+    if (st != VR_OK) return fail(c, st, "draw %u: %s", d, c->error.c_str());
+    const uint64_t T = D.num_indices / 3;
+    if (T && (!D.d_indices || !D.d_vertices || !D.d_corners))
+        return fail(c, VR_ERR_ARG, "draw %u: indices, vertices and corners are required", d);
+    if (((uintptr_t)D.d_vertices & 15) || ((uintptr_t)D.d_corners & 15))
+        return fail(c, VR_ERR_ARG, "draw %u: vertices and corners must be 16-byte aligned", d);
+    if (is_dynamic(D.strategy) && T && !D.d_plan)
+        return fail(c, VR_ERR_ARG, "draw %u: a dynamic draw in a frame needs its plan", d);
+    if (T && D.num_vertices == 0) need.index_error = true;
+    X = DrawDesc{};
+    X.idx = D.d_indices;
+    X.vtx = (const f4 *)D.d_vertices;
+    X.corners = (f4 *)D.d_corners;
+    X.counters = (unsigned long long *)D.d_counters;
+    X.plan = is_dynamic(D.strategy) ? D.d_plan : nullptr;
+    X.V = D.num_vertices;
+    X.T = (T && D.num_vertices == 0) ? 0u : (uint32_t)T;
+    X.batch_tris = D.batch_tris;
+    X.num_batches = is_dynamic(D.strategy) ? 0u : (uint32_t)((T + D.batch_tris - 1) / D.batch_tris);
+    X.shader = D.shader;
+    X.mode = frame_mode(D.strategy);
+    X.kind = sh.kind;
+    X.max_idx = r.max_idx;
+    X.max_uniq = r.max_uniq;
+    X.hash_bits = r.hash_bits;
+    X.probes = r.probes;
+    if (X.mode == kFrameNaive) {
+        need.slots += (3 * T + 255) / 256;
+        need.units += (3 * T + 255) / 256;
+    } else {
+        const uint64_t nb = is_dynamic(D.strategy) ? dyn_batch_bound(T, r.nu, D.batch_tris) : X.num_batches;
+        need.slots += nb;
+        if (X.mode == kFrameBallot) {
+            need.units += (nb + 3) / 4;
+            need.ballot_stride = std::max(need.ballot_stride, align16(64 * 48 + 3 * D.batch_tris));
+        } else {
+            need.units += nb;
+            need.unit_lds = std::max(need.unit_lds, dedup_lds_layout((int)X.mode, r.max_idx, r.max_uniq, r.hash_bits).total);
+        }
+    }
+    return VR_OK;
 }
 
 }  // namespace
@@ -588,59 +678,16 @@ vr_status vr_frame_create(vr_ctx *c, const vr_draw *draws, uint32_t n, const vr_
     if (n > VR_MAX_FRAME_DRAWS) return fail(c, VR_ERR_ARG, "a frame holds at most %d draws", VR_MAX_FRAME_DRAWS);
     if (n && (!draws || !shaders || ns == 0)) return fail(c, VR_ERR_ARG, "draws and shaders must not be NULL");
     std::vector<DrawDesc> desc(n);
-    uint64_t slots = 0;
-    uint32_t unit_lds = 256 * 48, ballot_stride = 0;
-    bool index_error = false;
+    FrameNeeds need;
     for (uint32_t d = 0; d < n; ++d) {
-        const vr_draw &D = draws[d];
-        if (D.shader >= ns) return fail(c, VR_ERR_ARG, "draw %u: shader %u out of range", d, D.shader);
-        vr_opts o{};
-        o.max_unique = D.max_unique;
-        o.d_plan = D.d_plan;
-        vr_outputs ov{};
-        ov.corners = D.d_corners;
-        ov.counters = D.d_counters;
-        Resolved r;
-        vr_status st = check_args(c, D.num_indices, &shaders[D.shader], D.strategy, D.batch_tris, &o, &ov, &r);
-        if (st != VR_OK) return fail(c, st, "draw %u: %s", d, c->error.c_str());
-        const uint64_t T = D.num_indices / 3;
-        if (T && (!D.d_indices || !D.d_vertices || !D.d_corners))
-            return fail(c, VR_ERR_ARG, "draw %u: indices, vertices and corners are required", d);
-        if (((uintptr_t)D.d_vertices & 15) || ((uintptr_t)D.d_corners & 15))
-            return fail(c, VR_ERR_ARG, "draw %u: vertices and corners must be 16-byte aligned", d);
-        if (is_dynamic(D.strategy) && T && !D.d_plan)
-            return fail(c, VR_ERR_ARG, "draw %u: a dynamic draw in a frame needs its plan", d);
-        if (T && D.num_vertices == 0) index_error = true;
-        DrawDesc &X = desc[d];
-        X.idx = D.d_indices;
-        X.vtx = (const f4 *)D.d_vertices;
-        X.corners = (f4 *)D.d_corners;
-        X.counters = (unsigned long long *)D.d_counters;
-        X.plan = is_dynamic(D.strategy) ? D.d_plan : nullptr;
-        X.V = D.num_vertices;
-        X.T = (T && D.num_vertices == 0) ? 0u : (uint32_t)T;
-        X.batch_tris = D.batch_tris;
-        X.num_batches = is_dynamic(D.strategy) ? 0u : (uint32_t)((T + D.batch_tris - 1) / D.batch_tris);
-        X.shader = D.shader;
-        X.mode = frame_mode(D.strategy);
-        X.kind = shaders[D.shader].kind;
-        X.max_idx = r.max_idx;
-        X.max_uniq = r.max_uniq;
-        X.hash_bits = r.hash_bits;
-        X.probes = r.probes;
-        if (X.mode == kFrameNaive) {
-            slots += (3 * T + 255) / 256;
-        } else {
-            slots += is_dynamic(D.strategy) ? dyn_batch_bound(T, r.nu, D.batch_tris) : X.num_batches;
-            if (X.mode == kFrameBallot) {
-                ballot_stride = std::max(ballot_stride, align16(64 * 48 + 3 * D.batch_tris));
-            } else {
-                unit_lds = std::max(unit_lds, dedup_lds_layout((int)X.mode, r.max_idx, r.max_uniq, r.hash_bits).total);
-            }
-        }
+        if (draws[d].shader >= ns) return fail(c, VR_ERR_ARG, "draw %u: shader %u out of range", d, draws[d].shader);
+        vr_status st = describe_draw(c, draws[d], shaders[draws[d].shader], d, desc[d], need);
+        if (st != VR_OK) return st;
     }
-    unit_lds = align16(std::max(unit_lds, 4 * ballot_stride));
-    const uint32_t lds_total = unit_lds + 4 * (n + 1);
+    const uint32_t unit_lds = align16(std::max(need.unit_lds, 4 * need.ballot_stride));
+    const uint32_t ballot_stride = need.ballot_stride, lds_total = need.lds_total(n);
+    const uint64_t slots = need.slots;
+    const bool index_error = need.index_error;
     if (lds_total > c->lds_limit)
         return fail(c, VR_ERR_ARG, "frame needs %u B of LDS per workgroup (limit %zu)", lds_total, c->lds_limit);
 
@@ -831,5 +878,673 @@ vr_status vr_kernel_times(vr_ctx *c, float *ms, uint32_t cap, uint32_t *count) {
 }
 
 const char *vr_last_error(const vr_ctx *c) { return c ? c->error.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"
+
+// ===========================================================================
+// Request server
+// ===========================================================================
+namespace {
+
+__global__ __launch_bounds__(256) void k_index_max(const uint32_t *idx, uint64_t n, uint32_t *out) {
+    __shared__ uint32_t tmp[256 / kWave];
+    uint32_t m = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+        m = max(m, idx[i]);
+    m = block_reduce_max<256>(m, tmp);
+    if (threadIdx.x == 0) atomicMax(out, m);
+}
+
+struct ServerMesh {
+    const uint32_t *idx = nullptr;
+    const float *vtx = nullptr;
+    uint32_t T = 0, V = 0;
+    std::map<uint64_t, uint32_t *> plans;   // (max_unique << 32 | batch_tris) -> plan of the whole mesh
+};
+
+struct ServerReq {
+    uint32_t mesh, num_tris, batch_tris, nu;
+    vr_strategy strategy;
+    vr_shader_params shader;
+    uint64_t inv = 0, units = 0;   // from the tick's counters
+};
+
+// Byte offsets of a tick's staging for n draws.  The head [0, cnt) is
+// uploaded (draw table, shader table, zeroed words), [words, end) is read
+// back (error word and per-draw counters); bases and totals follow.
+struct TickLayout {
+    size_t sh, words, cnt, end, ubase, sbase, dtot, total;
+    explicit TickLayout(uint32_t n) {
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        sh = al(sizeof(DrawDesc) * n);
+        words = sh + al(sizeof(vr_shader_params) * n);
+        cnt = words + 256;
+        end = cnt + al(32ull * n);
+        ubase = end;
+        sbase = ubase + al(4ull * (n + 1));
+        dtot = sbase + al(4ull * (n + 1));
+        total = dtot + al(8ull * n);
+    }
+};
+
+// Staging of one tick; reused by the tick max_inflight later, which is only
+// formed after this one retired.
+struct TickSlot {
+    hipEvent_t done = nullptr;
+    unsigned char *host = nullptr;   // pinned
+    unsigned char *dev = nullptr;
+    unsigned long long *agg = nullptr;
+    size_t agg_cap = 0;
+    uint32_t n = 0;
+    int launch_status = VR_OK;   // a tick that failed to launch retires with this
+};
+
+}  // namespace
+
+struct vr_server {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    vr_ctx *ctx = nullptr;   // plans are built through it, on the server's stream
+    vr_server_config cfg{};
+    unsigned char *arena = nullptr;
+    uint32_t *d_word = nullptr;
+    std::vector<TickSlot> slots;
+    std::map<uint32_t, int> per_cu;   // LDS bytes -> resident frame workgroups per CU
+    std::mutex m;
+    std::condition_variable cv_work, cv_done;
+    sched::Scheduler *sch = nullptr;
+    std::unordered_map<uint64_t, ServerReq> reqs;
+    std::vector<ServerMesh> meshes;
+    std::deque<uint64_t> done;   // finished, not yet polled
+    uint64_t plan_bytes = 0;
+    bool stop = false;
+    std::string error;
+    std::chrono::steady_clock::time_point t0;
+    std::thread worker;
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace {
+
+vr_status server_fail(vr_server *s, vr_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    s->error = buf;
+    return st;
+}
+
+// Plan of the whole mesh for (nu, batch_tris), built on first use.  Called
+// by the scheduler thread with the lock held.
+uint32_t *server_plan(vr_server *s, ServerMesh &M, uint32_t nu, uint32_t bt) {
+    const uint64_t key = (uint64_t)nu << 32 | bt;
+    auto it = M.plans.find(key);
+    if (it != M.plans.end()) return it->second;
+    uint32_t *plan = nullptr;
+    const size_t bytes = 4ull * (M.T + 2);
+    if (hipMalloc((void **)&plan, bytes) != hipSuccess) return nullptr;
+    if (vr_plan_dynamic(s->ctx, M.idx, 3ull * M.T, M.V, nu, bt, plan, M.T + 2) != VR_OK) {
+        (void)hipFree(plan);
+        return nullptr;
+    }
+    s->plan_bytes += bytes;
+    M.plans[key] = plan;
+    return plan;
+}
+
+int server_occupancy(vr_server *s, uint32_t lds) {
+    auto it = s->per_cu.find(lds);
+    if (it != s->per_cu.end()) return it->second;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_frame, kFrameNT, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    s->per_cu[lds] = per_cu;
+    return per_cu;
+}
+
+// Enqueues one tick over `jobs` (lock held).  A job that cannot be described
+// is finished with its error and processed as an empty draw.
+vr_status server_launch(vr_server *s, uint32_t tick, const std::vector<uint64_t> &jobs) {
+    vr_ctx *c = s->ctx;
+    TickSlot &S = s->slots[tick % s->slots.size()];
+    const uint32_t n = (uint32_t)jobs.size();
+    const TickLayout L(n);
+    DrawDesc *hd = (DrawDesc *)S.host;
+    vr_shader_params *hs = (vr_shader_params *)(S.host + L.sh);
+    memset(S.host + L.words, 0, 256);
+    unsigned long long *dcnt = (unsigned long long *)(S.dev + L.cnt);
+    FrameNeeds need;
+    for (uint32_t d = 0; d < n; ++d) {
+        sched::Job *j = s->sch->find(jobs[d]);
+        const ServerReq &R = s->reqs[jobs[d]];
+        ServerMesh &M = s->meshes[R.mesh];
+        hs[d] = R.shader;
+        vr_draw D{};
+        D.d_indices = M.idx;
+        D.num_indices = 3ull * R.num_tris;
+        D.d_vertices = M.vtx;
+        D.num_vertices = M.V;
+        D.shader = d;
+        D.strategy = R.strategy;
+        D.batch_tris = R.batch_tris;
+        D.max_unique = R.nu;
+        D.d_corners = (float *)(s->arena + j->off);
+        D.d_counters = (uint64_t *)(dcnt + 4ull * d);
+        if (is_dynamic(R.strategy) && R.num_tris) {
+            D.d_plan = server_plan(s, M, R.nu, R.batch_tris);
+            if (!D.d_plan) {
+                j->status = VR_ERR_OOM;
+                D.num_indices = 0;
+            }
+        }
+        if (describe_draw(c, D, hs[d], d, hd[d], need) != VR_OK) {
+            if (j->status == VR_OK) j->status = VR_ERR_ARG;
+            D.num_indices = 0;
+            D.d_plan = nullptr;
+            if (describe_draw(c, D, hs[d], d, hd[d], need) != VR_OK) return VR_ERR_ARG;
+        }
+    }
+    if (need.slots + 1 > S.agg_cap) {
+        if (S.agg) (void)hipFree(S.agg);
+        S.agg = nullptr;
+        S.agg_cap = std::max<size_t>(need.slots + 1, 2 * S.agg_cap);
+        if (hipMalloc((void **)&S.agg, 8 * S.agg_cap) != hipSuccess) {
+            S.agg_cap = 0;
+            return server_fail(s, VR_ERR_OOM, "tick aggregates: out of memory");
+        }
+    }
+    const uint32_t lds_total = need.lds_total(n);
+    const uint64_t want = std::max<uint64_t>(1, (need.units + kFrameChunk - 1) / kFrameChunk);
+    const uint64_t full = (uint64_t)c->num_cus * server_occupancy(s, lds_total);
+    CtxWords *dw = (CtxWords *)(S.dev + L.words);
+    FrameLaunch F{(const DrawDesc *)S.dev, n, (const vr_shader_params *)(S.dev + L.sh),
+                  (uint32_t *)(S.dev + L.ubase), (uint32_t *)(S.dev + L.sbase), S.agg,
+                  (unsigned long long *)(S.dev + L.dtot), align16(std::max(need.unit_lds, 4 * need.ballot_stride)),
+                  need.ballot_stride, lds_total, (uint32_t)std::min(want, full), &dw->err, &dw->total_inv};
+    S.n = n;
+    hipError_t e = hipMemcpyAsync(S.dev, S.host, L.cnt, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) {
+        enqueue_frame_kernels(F, s->stream);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S.host + L.words, S.dev + L.words, L.end - L.words, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(S.done, s->stream);
+    if (e != hipSuccess) return server_fail(s, VR_ERR_DEVICE, "tick launch: %s", hipGetErrorString(e));
+    return VR_OK;
+}
+
+// Retires finished ticks, oldest first (lock held).  Returns true if any.
+bool server_retire(vr_server *s) {
+    bool any = false;
+    while (s->sch->inflight() > 0) {
+        const uint32_t tick = s->sch->oldest_tick();
+        TickSlot &S = s->slots[tick % s->slots.size()];
+        const hipError_t q = S.launch_status == VR_OK ? hipEventQuery(S.done) : hipSuccess;
+        if (q == hipErrorNotReady) break;
+        const double t = s->now();
+        const std::vector<uint64_t> jobs = s->sch->oldest_jobs();
+        const TickLayout L(S.n);
+        const CtxWords *hw = (const CtxWords *)(S.host + L.words);
+        const unsigned long long *hc = (const unsigned long long *)(S.host + L.cnt);
+        int status = VR_OK;
+        if (S.launch_status != VR_OK) {
+            status = S.launch_status;
+        } else if (q != hipSuccess) {
+            status = VR_ERR_DEVICE;
+            s->error = std::string("tick failed: ") + hipGetErrorString(q);
+        } else if (hw->err) {
+            status = (int)hw->err;
+        }
+        for (uint32_t d = 0; d < jobs.size() && status == VR_OK; ++d) {
+            ServerReq &R = s->reqs[jobs[d]];
+            R.inv = hc[4ull * d];
+            R.units = hc[4ull * d + 1];
+        }
+        s->sch->retire_oldest(t, status);
+        for (uint32_t d = 0; d < jobs.size(); ++d) s->done.push_back(jobs[d]);
+        any = true;
+    }
+    return any;
+}
+
+}  // namespace
+
+namespace {
+
+// The scheduler thread: retire finished ticks, admit, launch; sleeps on the
+// condition variable, waking every 20 us while ticks are in flight.
+void server_loop(vr_server *s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->m);
+    std::vector<uint64_t> jobs;
+    for (;;) {
+        if (server_retire(s)) s->cv_done.notify_all();
+        if (s->stop && s->sch->idle()) break;
+        const double t = s->now();
+        s->sch->admit(t);
+        bool launched = false;
+        uint32_t tick = 0;
+        while (s->sch->next_tick(t, jobs, &tick)) {
+            TickSlot &S = s->slots[tick % s->slots.size()];
+            S.launch_status = VR_OK;
+            const vr_status st = server_launch(s, tick, jobs);
+            if (st != VR_OK) S.launch_status = st;
+            launched = true;
+        }
+        if (launched) continue;
+        if (s->sch->inflight() > 0) s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+        else s->cv_work.wait(lk);
+    }
+    s->cv_done.notify_all();
+}
+
+void server_free(vr_server *s) {
+    for (TickSlot &S : s->slots) {
+        if (S.done) (void)hipEventDestroy(S.done);
+        if (S.host) (void)hipHostFree(S.host);
+        if (S.dev) (void)hipFree(S.dev);
+        if (S.agg) (void)hipFree(S.agg);
+    }
+    for (ServerMesh &M : s->meshes)
+        for (auto &kv : M.plans) (void)hipFree(kv.second);
+    if (s->arena) (void)hipFree(s->arena);
+    if (s->d_word) (void)hipFree(s->d_word);
+    if (s->ctx) vr_destroy(s->ctx);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s->sch;
+    delete s;
+}
+
+sched::Policy server_policy(const vr_server_config &cfg) {
+    sched::Policy p;
+    p.budget = cfg.budget_bytes;
+    p.max_inflight = cfg.max_inflight;
+    p.max_tick_draws = cfg.max_tick_draws;
+    p.max_tick_tris = cfg.max_tick_tris;
+    return p;
+}
+
+vr_status check_server_config(const vr_server_config *in, vr_server_config &cfg, std::string &why) {
+    if (!in) {
+        why = "config is NULL";
+        return VR_ERR_ARG;
+    }
+    cfg = *in;
+    if (cfg.max_inflight == 0) cfg.max_inflight = 2;
+    if (cfg.max_tick_draws == 0) cfg.max_tick_draws = 1024;
+    if (cfg.max_inflight > 8) {
+        why = "max_inflight must be 1..8";
+        return VR_ERR_ARG;
+    }
+    if (cfg.max_tick_draws > VR_MAX_FRAME_DRAWS) {
+        why = "max_tick_draws must be 1..4096";
+        return VR_ERR_ARG;
+    }
+    if (cfg.budget_bytes < sched::Arena::kGranule) {
+        why = "budget_bytes below 256";
+        return VR_ERR_ARG;
+    }
+    return VR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vr_status vr_server_create(int device, const vr_server_config *cfg_in, vr_server **out) {
+    if (!out) return fail(nullptr, VR_ERR_ARG, "server pointer is NULL");
+    *out = nullptr;
+    vr_server_config cfg;
+    std::string why;
+    if (check_server_config(cfg_in, cfg, why) != VR_OK) return fail(nullptr, VR_ERR_ARG, "%s", why.c_str());
+    vr_server *s = new vr_server();
+    s->device = device;
+    s->cfg = cfg;
+    s->t0 = std::chrono::steady_clock::now();
+    s->sch = new sched::Scheduler(server_policy(cfg));
+    if (vr_create(&s->ctx, device, nullptr) != VR_OK) {
+        server_free(s);
+        return fail(nullptr, VR_ERR_DEVICE, "%s", vr_last_error(nullptr));
+    }
+    DeviceGuard g(device);
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+        s->stream = nullptr;
+        server_free(s);
+        return fail(nullptr, VR_ERR_DEVICE, "stream creation failed");
+    }
+    vr_set_stream(s->ctx, s->stream);
+    if (hipMalloc((void **)&s->arena, cfg.budget_bytes) != hipSuccess) {
+        s->arena = nullptr;
+        server_free(s);
+        return fail(nullptr, VR_ERR_OOM, "arena of %llu bytes: out of memory", (unsigned long long)cfg.budget_bytes);
+    }
+    bool ok = hipMalloc((void **)&s->d_word, 256) == hipSuccess;
+    const TickLayout L(cfg.max_tick_draws);
+    s->slots.resize(cfg.max_inflight);
+    for (TickSlot &S : s->slots) {
+        if (!ok) break;
+        ok = hipEventCreateWithFlags(&S.done, hipEventDisableTiming) == hipSuccess &&
+             hipHostMalloc((void **)&S.host, L.end, hipHostMallocDefault) == hipSuccess &&
+             hipMalloc((void **)&S.dev, L.total) == hipSuccess;
+    }
+    if (!ok) {
+        server_free(s);
+        return fail(nullptr, VR_ERR_OOM, "server staging allocation failed");
+    }
+    s->worker = std::thread(server_loop, s);
+    *out = s;
+    return VR_OK;
+}
+
+vr_status vr_server_add_mesh(vr_server *s, const uint32_t *d_idx, uint64_t num_indices, const float *d_vtx,
+                             uint32_t V, uint32_t *mesh) {
+    if (!s || !mesh) return VR_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->m);
+    if (num_indices % 3 != 0 || num_indices > VR_MAX_INDICES)
+        return server_fail(s, VR_ERR_ARG, "num_indices must be a multiple of 3 below 3*2^30");
+    if (num_indices && (!d_idx || !d_vtx)) return server_fail(s, VR_ERR_ARG, "indices or vertices are NULL");
+    if ((uintptr_t)d_vtx & 15) return server_fail(s, VR_ERR_ARG, "vertices must be 16-byte aligned");
+    if (s->meshes.size() >= (1u << 20)) return server_fail(s, VR_ERR_ARG, "too many meshes");
+    if (num_indices) {
+        // every index below V, checked once so that no request can fault
+        DeviceGuard g(s->device);
+        hipStream_t st = nullptr;
+        uint32_t mx = 0;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipMemsetAsync(s->d_word, 0, 4, st);
+        if (e == hipSuccess) {
+            const uint64_t blocks = std::min<uint64_t>(4096, (num_indices + 255) / 256);
+            hipLaunchKernelGGL(k_index_max, dim3((uint32_t)blocks), dim3(256), 0, st, d_idx, num_indices, s->d_word);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(&mx, s->d_word, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (st) (void)hipStreamDestroy(st);
+        if (e != hipSuccess) return server_fail(s, VR_ERR_DEVICE, "index check: %s", hipGetErrorString(e));
+        if (mx >= V) return server_fail(s, VR_ERR_INDEX_RANGE, "index %u >= num_vertices %u", mx, V);
+    }
+    ServerMesh M;
+    M.idx = d_idx;
+    M.vtx = d_vtx;
+    M.T = (uint32_t)(num_indices / 3);
+    M.V = V;
+    *mesh = (uint32_t)s->meshes.size();
+    s->meshes.push_back(std::move(M));
+    return VR_OK;
+}
+
+vr_status vr_server_submit(vr_server *s, const vr_request *r, uint64_t *ticket) {
+    if (!s || !r || !ticket) return VR_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->m);
+    if (s->stop) return server_fail(s, VR_ERR_BUSY, "the server is shutting down");
+    if (r->mesh >= s->meshes.size()) return server_fail(s, VR_ERR_ARG, "unknown mesh %u", r->mesh);
+    const ServerMesh &M = s->meshes[r->mesh];
+    if (r->num_tris > M.T) return server_fail(s, VR_ERR_ARG, "num_tris %u beyond the mesh (%u)", r->num_tris, M.T);
+    // the same rules as vr_process_draw, and the request alone must fit a tick
+    ServerReq R{};
+    R.mesh = r->mesh;
+    R.num_tris = r->num_tris;
+    R.batch_tris = r->batch_tris;
+    R.strategy = r->strategy;
+    R.shader = r->shader;
+    vr_opts o{};
+    o.max_unique = r->max_unique;
+    vr_outputs ov{};
+    Resolved res;
+    if (check_args(s->ctx, 3ull * r->num_tris, &r->shader, r->strategy, r->batch_tris, &o, &ov, &res) != VR_OK)
+        return server_fail(s, VR_ERR_ARG, "%s", s->ctx->error.c_str());
+    R.nu = is_dynamic(r->strategy) ? res.nu : 0;
+    FrameNeeds need;
+    DrawDesc X;
+    vr_draw D{};
+    D.d_indices = M.idx;
+    D.num_indices = 3ull * r->num_tris;
+    D.d_vertices = M.vtx;
+    D.num_vertices = M.V;
+    D.strategy = r->strategy;
+    D.batch_tris = r->batch_tris;
+    D.max_unique = R.nu;
+    D.d_plan = M.idx;          // stands in for the plan during validation
+    D.d_corners = (float *)s->arena;
+    if (describe_draw(s->ctx, D, r->shader, 0, X, need) != VR_OK)
+        return server_fail(s, VR_ERR_ARG, "%s", s->ctx->error.c_str());
+    if (need.lds_total(s->cfg.max_tick_draws) > s->ctx->lds_limit)
+        return server_fail(s, VR_ERR_ARG, "the request needs more LDS than a tick allows");
+    const uint64_t bytes = 144ull * r->num_tris;
+    uint64_t t = 0;
+    const int st = s->sch->submit(r->user, bytes, r->num_tris, s->now(), &t);
+    if (st != sched::kOk)
+        return server_fail(s, (vr_status)st, "the request's %llu output bytes exceed the budget",
+                           (unsigned long long)bytes);
+    s->reqs[t] = R;
+    *ticket = t;
+    s->cv_work.notify_one();
+    return VR_OK;
+}
+
+vr_status vr_server_poll(vr_server *s, vr_completion *out, uint32_t cap, uint32_t *count, uint32_t timeout_ms) {
+    if (!s || !count || (cap && !out)) return VR_ERR_ARG;
+    std::unique_lock<std::mutex> lk(s->m);
+    if (s->done.empty() && timeout_ms)
+        s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), [s] { return !s->done.empty(); });
+    uint32_t k = 0;
+    while (k < cap && !s->done.empty()) {
+        const uint64_t t = s->done.front();
+        s->done.pop_front();
+        const sched::Job *j = s->sch->find(t);
+        if (!j) continue;   // released before it was polled
+        const ServerReq &R = s->reqs[t];
+        vr_completion &c = out[k++];
+        c.ticket = t;
+        c.user = j->user;
+        c.status = j->status;
+        c.tick = j->tick;
+        c.num_tris = R.num_tris;
+        c.invocations = R.inv;
+        c.units = R.units;
+        c.d_corners = j->has_mem ? (const float *)(s->arena + j->off) : nullptr;
+        c.t_submit = j->t_submit;
+        c.t_admit = j->t_admit;
+        c.t_launch = j->t_launch;
+        c.t_done = j->t_done;
+    }
+    *count = k;
+    return VR_OK;
+}
+
+vr_status vr_server_release(vr_server *s, uint64_t ticket) {
+    if (!s) return VR_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->m);
+    const int st = s->sch->release(ticket);
+    if (st == sched::kArg) return server_fail(s, VR_ERR_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    if (st == sched::kBusy) return server_fail(s, VR_ERR_BUSY, "request %llu has not finished", (unsigned long long)ticket);
+    s->reqs.erase(ticket);
+    s->cv_work.notify_one();
+    return VR_OK;
+}
+
+vr_status vr_server_fetch(vr_server *s, uint64_t ticket, void *dst, uint64_t bytes) {
+    if (!s || (!dst && bytes)) return VR_ERR_ARG;
+    const float *src = nullptr;
+    uint64_t need = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->m);
+        const sched::Job *j = s->sch->find(ticket);
+        if (!j) return server_fail(s, VR_ERR_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+        if (j->state != sched::State::Done) return server_fail(s, VR_ERR_BUSY, "request has not finished");
+        need = 144ull * s->reqs[ticket].num_tris;
+        if (bytes < need) return server_fail(s, VR_ERR_CAPACITY, "need %llu bytes", (unsigned long long)need);
+        src = j->has_mem ? (const float *)(s->arena + j->off) : nullptr;
+    }
+    if (!src || need == 0) return VR_OK;
+    // the request stays reserved until the caller releases it, so the copy
+    // runs outside the lock
+    DeviceGuard g(s->device);
+    if (hipMemcpy(dst, src, need, hipMemcpyDeviceToHost) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(s->m);
+        return server_fail(s, VR_ERR_DEVICE, "result copy failed");
+    }
+    return VR_OK;
+}
+
+vr_status vr_server_cancel(vr_server *s, uint64_t ticket) {
+    if (!s) return VR_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->m);
+    const int st = s->sch->cancel(ticket, s->now());
+    if (st == sched::kArg) return server_fail(s, VR_ERR_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    if (st == sched::kBusy) return server_fail(s, VR_ERR_BUSY, "request %llu was launched", (unsigned long long)ticket);
+    s->done.push_back(ticket);
+    s->cv_done.notify_all();
+    s->cv_work.notify_one();
+    return VR_OK;
+}
+
+vr_status vr_server_stats_get(vr_server *s, vr_server_stats *o) {
+    if (!s || !o) return VR_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->m);
+    const sched::Counts &n = s->sch->counts();
+    *o = vr_server_stats{};
+    o->submitted = n.submitted;
+    o->completed = n.completed;
+    o->cancelled = n.cancelled;
+    o->rejected = n.rejected;
+    o->ticks = n.ticks;
+    o->budget_bytes = s->sch->arena().capacity();
+    o->reserved_bytes = s->sch->arena().used();
+    o->peak_reserved_bytes = s->sch->arena().peak();
+    o->pending = s->sch->pending();
+    o->admitted = s->sch->admitted();
+    o->inflight_ticks = s->sch->inflight();
+    o->max_pending = n.max_pending;
+    o->max_tick_draws = n.max_tick_draws;
+    o->admission_blocked = n.admission_blocked;
+    o->plan_bytes = s->plan_bytes;
+    return VR_OK;
+}
+
+void vr_server_destroy(vr_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->m);
+        s->stop = true;
+        for (uint64_t t : s->sch->cancel_all(s->now())) s->done.push_back(t);
+        s->cv_work.notify_one();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    DeviceGuard g(s->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    server_free(s);
+}
+
+const char *vr_server_last_error(const vr_server *s) { return s ? s->error.c_str() : g_create_error.c_str(); }
+
+// The same policy on a simulated clock and device (host only).
+vr_status vr_server_simulate(const vr_server_config *cfg_in, const vr_sim_request *rq, uint32_t n, double fixed_s,
+                             double per_tri_s, vr_sim_result *res, vr_server_stats *stats) {
+    vr_server_config cfg;
+    std::string why;
+    if (check_server_config(cfg_in, cfg, why) != VR_OK) return fail(nullptr, VR_ERR_ARG, "%s", why.c_str());
+    if (n && (!rq || !res)) return fail(nullptr, VR_ERR_ARG, "requests and results must not be NULL");
+    for (uint32_t i = 1; i < n; ++i)
+        if (rq[i].arrival < rq[i - 1].arrival) return fail(nullptr, VR_ERR_ARG, "requests must be sorted by arrival");
+    sched::Scheduler sch(server_policy(cfg));
+    std::vector<uint64_t> ticket(n, 0);
+    std::unordered_map<uint64_t, uint32_t> index;
+    for (uint32_t i = 0; i < n; ++i) res[i] = vr_sim_result{VR_OK, 0, -1.0, -1.0, -1.0, -1.0, 0};
+    std::deque<std::pair<double, uint32_t>> ticks;   // end time, tick id (device runs them in order)
+    std::multimap<double, uint64_t> releases, cancels;
+    double device_free = 0.0;
+    uint32_t next = 0;
+    std::vector<uint64_t> jobs;
+    auto finish = [&](uint64_t t, double now) {
+        const sched::Job *j = sch.find(t);
+        vr_sim_result &r = res[index[t]];
+        r.status = j->status;
+        r.tick = j->tick;
+        r.t_admit = j->t_admit;
+        r.t_launch = j->t_launch;
+        r.t_done = j->t_done;
+        r.offset = j->off;
+        const uint32_t i = index[t];
+        releases.emplace(now + std::max(0.0, rq[i].hold), t);
+    };
+    const double inf = 1e300;
+    for (;;) {
+        const double ta = next < n ? rq[next].arrival : inf;
+        const double tt = ticks.empty() ? inf : ticks.front().first;
+        const double tr = releases.empty() ? inf : releases.begin()->first;
+        const double tc = cancels.empty() ? inf : cancels.begin()->first;
+        const double now = std::min(std::min(ta, tt), std::min(tr, tc));
+        if (now >= inf) break;
+        // events at `now`: tick ends, releases, cancellations, arrivals
+        while (!ticks.empty() && ticks.front().first <= now) {
+            const std::vector<uint64_t> done = sch.oldest_jobs();
+            sch.retire_oldest(ticks.front().first, VR_OK);
+            for (uint64_t t : done) finish(t, ticks.front().first);
+            ticks.pop_front();
+        }
+        while (!releases.empty() && releases.begin()->first <= now) {
+            const uint64_t t = releases.begin()->second;
+            res[index[t]].t_release = releases.begin()->first;
+            sch.release(t);
+            releases.erase(releases.begin());
+        }
+        while (!cancels.empty() && cancels.begin()->first <= now) {
+            const uint64_t t = cancels.begin()->second;
+            if (sch.cancel(t, cancels.begin()->first) == sched::kOk) {
+                const sched::Job *j = sch.find(t);
+                vr_sim_result &r = res[index[t]];
+                r.status = j->status;
+                r.t_admit = j->t_admit;
+                r.t_done = j->t_done;
+                r.offset = j->off;
+                res[index[t]].t_release = cancels.begin()->first;
+                sch.release(t);
+            }
+            cancels.erase(cancels.begin());
+        }
+        while (next < n && rq[next].arrival <= now) {
+            uint64_t t = 0;
+            const int st = sch.submit(next, rq[next].bytes, rq[next].num_tris, rq[next].arrival, &t);
+            if (st != sched::kOk) {
+                res[next].status = st;
+            } else {
+                ticket[next] = t;
+                index[t] = next;
+                if (rq[next].cancel_at >= 0.0) cancels.emplace(std::max(rq[next].cancel_at, rq[next].arrival), t);
+            }
+            ++next;
+        }
+        sch.admit(now);
+        uint32_t tick = 0;
+        while (sch.next_tick(now, jobs, &tick)) {
+            uint64_t tris = 0;
+            for (uint64_t t : jobs) tris += sch.find(t)->tris;
+            const double start = std::max(now, device_free);
+            device_free = start + fixed_s + per_tri_s * (double)tris;
+            ticks.push_back({device_free, tick});
+        }
+    }
+    if (stats) {
+        const sched::Counts &c = sch.counts();
+        *stats = vr_server_stats{};
+        stats->submitted = c.submitted;
+        stats->completed = c.completed;
+        stats->cancelled = c.cancelled;
+        stats->rejected = c.rejected;
+        stats->ticks = c.ticks;
+        stats->budget_bytes = sch.arena().capacity();
+        stats->reserved_bytes = sch.arena().used();
+        stats->peak_reserved_bytes = sch.arena().peak();
+        stats->max_pending = c.max_pending;
+        stats->max_tick_draws = c.max_tick_draws;
+        stats->admission_blocked = c.admission_blocked;
+    }
+    return VR_OK;
+}
 
 }  // extern "C"

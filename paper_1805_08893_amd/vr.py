@@ -16,7 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvr.so")
 
-VR_OK, VR_ERR_ARG, VR_ERR_INDEX_RANGE, VR_ERR_CAPACITY, VR_ERR_OOM, VR_ERR_DEVICE, VR_ERR_BUSY = range(7)
+(VR_OK, VR_ERR_ARG, VR_ERR_INDEX_RANGE, VR_ERR_CAPACITY, VR_ERR_OOM, VR_ERR_DEVICE, VR_ERR_BUSY,
+ VR_CANCELLED) = range(8)
 (VR_NAIVE, VR_STATIC_BALLOT, VR_STATIC_SORT, VR_STATIC_HASH, VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH,
  VR_DYN_BALLOT) = range(8)
 STRATEGIES = {"naive": VR_NAIVE, "static_ballot": VR_STATIC_BALLOT, "static_sort": VR_STATIC_SORT,
@@ -28,7 +29,9 @@ OUT_FLOATS = 12
 
 EXPORTS = ["vr_create", "vr_destroy", "vr_set_stream", "vr_check_args", "vr_plan_dynamic", "vr_process_draw",
            "vr_sync", "vr_frame_create", "vr_frame_run", "vr_frame_destroy", "vr_process_draws", "vr_autotune",
-           "vr_set_kernel_timing", "vr_kernel_times", "vr_last_error"]
+           "vr_set_kernel_timing", "vr_kernel_times", "vr_last_error", "vr_server_create", "vr_server_add_mesh",
+           "vr_server_submit", "vr_server_poll", "vr_server_release", "vr_server_fetch", "vr_server_cancel", "vr_server_stats_get",
+           "vr_server_destroy", "vr_server_last_error", "vr_server_simulate"]
 
 
 class vr_opts(C.Structure):
@@ -55,6 +58,45 @@ class vr_draw(C.Structure):
                 ("num_vertices", C.c_uint32), ("shader", C.c_uint32), ("strategy", C.c_int),
                 ("batch_tris", C.c_uint32), ("max_unique", C.c_uint32), ("d_plan", C.c_void_p),
                 ("d_corners", C.c_void_p), ("d_counters", C.c_void_p)]
+
+
+class vr_server_config(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("max_inflight", C.c_uint32), ("max_tick_draws", C.c_uint32),
+                ("max_tick_tris", C.c_uint64)]
+
+
+class vr_request(C.Structure):
+    _fields_ = [("mesh", C.c_uint32), ("num_tris", C.c_uint32), ("strategy", C.c_int), ("batch_tris", C.c_uint32),
+                ("max_unique", C.c_uint32), ("pad", C.c_uint32), ("user", C.c_uint64),
+                ("shader", vr_shader_params)]
+
+
+class vr_completion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("user", C.c_uint64), ("status", C.c_int32), ("tick", C.c_uint32),
+                ("num_tris", C.c_uint64), ("invocations", C.c_uint64), ("units", C.c_uint64),
+                ("d_corners", C.c_void_p), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_launch", C.c_double), ("t_done", C.c_double)]
+
+
+class vr_server_stats(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in (
+        "submitted", "completed", "cancelled", "rejected", "ticks", "budget_bytes", "reserved_bytes",
+        "peak_reserved_bytes", "pending", "admitted", "inflight_ticks", "max_pending", "max_tick_draws",
+        "admission_blocked", "plan_bytes")]
+
+
+class vr_sim_request(C.Structure):
+    _fields_ = [("arrival", C.c_double), ("cancel_at", C.c_double), ("hold", C.c_double),
+                ("num_tris", C.c_uint64), ("bytes", C.c_uint64)]
+
+
+class vr_sim_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("tick", C.c_uint32), ("t_admit", C.c_double), ("t_launch", C.c_double),
+                ("t_done", C.c_double), ("t_release", C.c_double), ("offset", C.c_uint64)]
+
+
+def _struct_dict(x):
+    return {k: getattr(x, k) for k, _ in x._fields_}
 
 
 class VrError(RuntimeError):
@@ -106,6 +148,24 @@ def lib():
         L.vr_kernel_times.restype = C.c_int
         L.vr_last_error.argtypes = [P]
         L.vr_last_error.restype = C.c_char_p
+        L.vr_server_create.argtypes = [C.c_int, C.POINTER(vr_server_config), C.POINTER(C.c_void_p)]
+        L.vr_server_add_mesh.argtypes = [P, P, C.c_uint64, P, C.c_uint32, C.POINTER(C.c_uint32)]
+        L.vr_server_submit.argtypes = [P, C.POINTER(vr_request), C.POINTER(C.c_uint64)]
+        L.vr_server_poll.argtypes = [P, C.POINTER(vr_completion), C.c_uint32, C.POINTER(C.c_uint32), C.c_uint32]
+        L.vr_server_release.argtypes = [P, C.c_uint64]
+        L.vr_server_cancel.argtypes = [P, C.c_uint64]
+        L.vr_server_fetch.argtypes = [P, C.c_uint64, P, C.c_uint64]
+        L.vr_server_stats_get.argtypes = [P, C.POINTER(vr_server_stats)]
+        L.vr_server_simulate.argtypes = [C.POINTER(vr_server_config), C.POINTER(vr_sim_request), C.c_uint32,
+                                         C.c_double, C.c_double, C.POINTER(vr_sim_result),
+                                         C.POINTER(vr_server_stats)]
+        for f in ("vr_server_create", "vr_server_add_mesh", "vr_server_submit", "vr_server_poll",
+                  "vr_server_release", "vr_server_fetch", "vr_server_cancel", "vr_server_stats_get", "vr_server_simulate"):
+            getattr(L, f).restype = C.c_int
+        L.vr_server_destroy.argtypes = [P]
+        L.vr_server_destroy.restype = None
+        L.vr_server_last_error.argtypes = [P]
+        L.vr_server_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -310,3 +370,84 @@ def units_bound(strategy, num_tris, batch_tris):
     if strategy in (VR_STATIC_SORT, VR_STATIC_HASH):
         return (num_tris + batch_tris - 1) // batch_tris
     return num_tris
+
+
+# ------------------------------------------------------------- request server
+def make_server_config(budget_bytes, max_inflight=0, max_tick_draws=0, max_tick_tris=0) -> vr_server_config:
+    return vr_server_config(int(budget_bytes), int(max_inflight), int(max_tick_draws), int(max_tick_tris))
+
+
+def vr_server_create(device, cfg):
+    h = C.c_void_p()
+    st = lib().vr_server_create(device, C.byref(cfg), C.byref(h))
+    if st != VR_OK:
+        raise VrError(st, vr_last_error(None))
+    return h
+
+
+def vr_server_last_error(server):
+    msg = lib().vr_server_last_error(server)
+    return msg.decode() if msg else ""
+
+
+def vr_server_add_mesh(server, indices, vertices):
+    """Registers a resident mesh (torch device tensors kept alive by the caller)."""
+    m = C.c_uint32()
+    V = vertices.shape[0] if vertices.dim() == 2 else vertices.numel() // 8
+    st = lib().vr_server_add_mesh(server, _ptr(indices), indices.numel(), _ptr(vertices), V, C.byref(m))
+    return st, m.value
+
+
+def make_request(mesh, num_tris, shader, strategy, batch_tris, max_unique=0, user=0) -> vr_request:
+    sh = shader if isinstance(shader, vr_shader_params) else make_shader(shader)
+    return vr_request(mesh, num_tris, strategy, batch_tris, max_unique, 0, user, sh)
+
+
+def vr_server_submit(server, request):
+    t = C.c_uint64()
+    st = lib().vr_server_submit(server, C.byref(request), C.byref(t))
+    return st, t.value
+
+
+def vr_server_poll(server, cap=256, timeout_ms=0):
+    """(status, list of completion dicts)."""
+    buf = (vr_completion * cap)()
+    n = C.c_uint32()
+    st = lib().vr_server_poll(server, buf, cap, C.byref(n), timeout_ms)
+    return st, [_struct_dict(buf[i]) for i in range(n.value)]
+
+
+def vr_server_release(server, ticket):
+    return lib().vr_server_release(server, ticket)
+
+
+def vr_server_fetch(server, ticket, num_tris):
+    """(status, float32[3 num_tris][12] numpy array) of a finished request."""
+    out = np.empty((3 * num_tris, OUT_FLOATS), dtype=np.float32)
+    st = lib().vr_server_fetch(server, ticket, out.ctypes.data, out.nbytes)
+    return st, out
+
+
+def vr_server_cancel(server, ticket):
+    return lib().vr_server_cancel(server, ticket)
+
+
+def vr_server_stats_get(server):
+    o = vr_server_stats()
+    st = lib().vr_server_stats_get(server, C.byref(o))
+    return st, _struct_dict(o)
+
+
+def vr_server_destroy(server):
+    lib().vr_server_destroy(server)
+
+
+def vr_server_simulate(cfg, requests, tick_fixed_s, tick_s_per_tri):
+    """requests: list of (arrival, num_tris, bytes, cancel_at, hold), sorted by
+    arrival.  Returns (status, list of result dicts, stats dict)."""
+    n = len(requests)
+    rq = (vr_sim_request * max(1, n))(*[vr_sim_request(a, c, h, t, b) for a, t, b, c, h in requests])
+    res = (vr_sim_result * max(1, n))()
+    stats = vr_server_stats()
+    st = lib().vr_server_simulate(C.byref(cfg), rq, n, tick_fixed_s, tick_s_per_tri, res, C.byref(stats))
+    return st, [_struct_dict(res[i]) for i in range(n)], _struct_dict(stats)

@@ -424,3 +424,53 @@ def grid2048_offset64(order: str = "hilbert", seed: int = 4, n: int = 2048):
     triangle order with the 64-iteration normal-offset shader."""
     m = grid_mesh(n, n, seed, order)
     return m, shader_for_mesh(m, SHADER_OFFSET, seed, iterations=64)
+
+
+# --------------------------------------------------------------------------
+# Serving workload: a pool of resident meshes and a Poisson request stream
+# --------------------------------------------------------------------------
+def serving_bases(seed: int = 11, grid_n: int = 1024, ico_level: int = 8):
+    """Base meshes of the request pool: two grids of grid_n x grid_n vertices
+    (about 2.09M triangles at 1024) and two icospheres (1.31M triangles at
+    level 8), one of each in Hilbert and one in scan order."""
+    return [grid_mesh(grid_n, grid_n, seed, "hilbert"), grid_mesh(grid_n, grid_n, seed + 1, "scan"),
+            icosphere_mesh(ico_level, seed + 2, "hilbert"), icosphere_mesh(ico_level, seed + 3, "scan")]
+
+
+def serving_pool(bases, seed: int = 12, n: int = 200, min_tris: int = 1000):
+    """n meshes, each a contiguous window (base, first triangle, triangles)
+    of a base index buffer; the first two windows of every base start at 0
+    and span the whole base, the rest start at a seeded triangle in the first
+    half and run to the end."""
+    rng = np.random.default_rng(seed)
+    pool = []
+    for m in range(n):
+        b = m % len(bases)
+        T = bases[b].num_tris
+        start = 0 if m < 2 * len(bases) else int(rng.integers(0, max(1, min(T // 2, T - min_tris))))
+        pool.append((b, start, T - start))
+    return pool
+
+
+def serving_trace(pool, seed: int = 13, n: int = 2000, rate: float = 500.0, size_lo: int = 1000,
+                  size_hi: int = 2_000_000, lights=(1, 16)):
+    """Poisson arrivals at `rate` per second; sizes log-normal with median
+    sqrt(size_lo * size_hi) and sigma ln(size_hi / size_lo) / 4, clipped to
+    [size_lo, size_hi]; each request takes the first `size` triangles of a
+    pool mesh drawn uniformly among those long enough (the longest when none
+    is); Phong lighting with a uniform number of lights."""
+    rng = np.random.default_rng(seed)
+    arrival = np.cumsum(rng.exponential(1.0 / rate, n))
+    arrival -= arrival[0]
+    mu, sigma = 0.5 * np.log(size_lo * size_hi), np.log(size_hi / size_lo) / 4
+    size = np.clip(np.exp(rng.normal(mu, sigma, n)), size_lo, size_hi).astype(np.int64)
+    lens = np.array([p[2] for p in pool])
+    mesh = np.empty(n, dtype=np.int64)
+    for i in range(n):
+        ok = np.nonzero(lens >= size[i])[0]
+        if ok.size == 0:
+            ok = np.nonzero(lens == lens.max())[0]
+            size[i] = lens.max()
+        mesh[i] = ok[rng.integers(0, ok.size)]
+    nl = rng.integers(lights[0], lights[1] + 1, n)
+    return {"arrival": arrival, "size": size, "mesh": mesh, "lights": nl}

@@ -390,3 +390,22 @@ def test_corners_equal_naive_shading_all_strategies():
         np.testing.assert_array_equal(r["verts"][r["tris"]], ref)
         inv, U = int(r["counters"][0]), int(r["counters"][2])
         assert U <= inv <= len(m.indices)
+
+
+def test_plan_of_a_prefix_is_the_cut_plan():
+    """Greedy batching closes a batch without looking past it, so the plan of
+    the first T' triangles equals the plan of the whole stream cut at T'
+    (batches starting before T', the last one ending at T').  The request
+    server relies on this to serve prefixes of resident meshes."""
+    meshes = [W.grid_mesh(30, 20, 3, "hilbert"), W.icosphere_mesh(3, 4, "random"),
+              W.grid_mesh(25, 25, 5, "scan")]
+    rng = np.random.default_rng(9)
+    for m in meshes:
+        for nu, bt in ((9, 3), (64, 21), (256, 256), (341, 512)):
+            full = vro.plan_dynamic(m.indices, m.num_verts, nu, bt)
+            for Tp in list(rng.integers(1, m.num_tris, 12)) + [1, m.num_tris]:
+                Tp = int(Tp)
+                own = vro.plan_dynamic(m.indices[:3 * Tp], m.num_verts, nu, bt)
+                starts = full[:-1]
+                cut = np.concatenate([starts[starts < Tp], [Tp]]).astype(np.uint32)
+                assert np.array_equal(own, cut), (m.name, nu, bt, Tp)
