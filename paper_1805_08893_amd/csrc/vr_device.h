@@ -159,6 +159,32 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
     return before + incl - v;
 }
 
+// Workgroup-wide min and max together; `tmp` holds 2*NT/64 words.  Contains
+// barriers: call uniformly.
+template <int NT>
+__device__ __forceinline__ void block_reduce_minmax(uint32_t &mn, uint32_t &mx, uint32_t *tmp) {
+    constexpr int NW = NT / kWave;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        mn = min(mn, (uint32_t)__shfl_xor(mn, d, kWave));
+        mx = max(mx, (uint32_t)__shfl_xor(mx, d, kWave));
+    }
+    __syncthreads();
+    if (lane_id() == 0) {
+        tmp[threadIdx.x / kWave] = mn;
+        tmp[NW + threadIdx.x / kWave] = mx;
+    }
+    __syncthreads();
+    mn = tmp[0];
+    mx = tmp[NW];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
+        mn = min(mn, tmp[i]);
+        mx = max(mx, tmp[NW + i]);
+    }
+    __syncthreads();
+}
+
 // Workgroup-wide min / max (contain barriers: call uniformly).
 template <int NT>
 __device__ __forceinline__ uint32_t block_reduce_min(uint32_t v, uint32_t *tmp) {

@@ -124,7 +124,7 @@ __device__ __forceinline__ void frame_unit_kind(const DrawDesc &D, const DrawArg
         const uint32_t w = threadIdx.x / kWave;
         const uint32_t b = 4 * local + w;
         unsigned char *mine = smem + w * ballot_stride;
-        if (b < nb) ballot_batch<KIND>(A, sh, b, nb, (f4 *)mine, mine + 64 * 48);
+        if (b < nb) ballot_batch<KIND>(A, sh, b, nb, mine);
         __syncthreads();
         break;
     }

@@ -220,8 +220,15 @@ __host__ __device__ inline uint32_t pow2_ceil(uint32_t x) {
     return p;
 }
 
+// Count groups per digit of the sort's radix passes: rounds x wavefronts,
+// padded to whole words.
+__host__ __device__ inline uint32_t sort_groups(uint32_t max_idx, uint32_t nt) {
+    const uint32_t g = (max_idx + nt - 1) / nt * (nt / 64);
+    return (g + 3u) & ~3u;
+}
+
 __host__ __device__ inline DedupLds dedup_lds_layout(int mode, uint32_t max_idx, uint32_t max_uniq,
-                                                     uint32_t hash_bits) {
+                                                     uint32_t hash_bits, uint32_t nt) {
     DedupLds L{};
     uint32_t off = 0;
     L.keys = off;  off += align16(4 * max_idx);
@@ -236,10 +243,9 @@ __host__ __device__ inline DedupLds dedup_lds_layout(int mode, uint32_t max_idx,
     }
     L.uniq = off; off += align16(4 * max_uniq);
     L.sv = off;
-    // the sort's digit-count table (256 digits x rounds x waves, uint16) lives
-    // in the shaded-vertex area before shading
-    // (rounds x waves <= ceil(max_idx / 64) + 8 for any workgroup of <= 512)
-    off += mode == kSort ? max(48 * max_uniq, 2u * 256u * ((max_idx + 63) / 64 + 8)) : 48 * max_uniq;
+    // the sort's per-digit counts (uint8) and offsets (uint16), 256 digits x
+    // sort_groups entries each, live in the shaded-vertex area before shading
+    off += mode == kSort ? max(48 * max_uniq, 3u * 256u * sort_groups(max_idx, nt)) : 48 * max_uniq;
     L.tmp = off;  off += 64;
     L.total = off;
     return L;
@@ -279,7 +285,7 @@ __device__ __forceinline__ uint32_t rank_flagged(uint32_t n, uint32_t *s_tmp, Fl
 template <int NT, int MODE, int KIND>
 __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_params &sh, uint32_t u, uint32_t nb,
                                            unsigned char *smem) {
-    const DedupLds L = dedup_lds_layout(MODE, A.max_idx, A.max_uniq, A.hash_bits);
+    const DedupLds L = dedup_lds_layout(MODE, A.max_idx, A.max_uniq, A.hash_bits, NT);
     uint32_t *s_keys = (uint32_t *)(smem + L.keys);
     uint32_t *s_local = (uint32_t *)(smem + L.local);
     uint32_t *s_uniq = (uint32_t *)(smem + L.uniq);
@@ -306,14 +312,22 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
             // 8-bit digits of (index - batch minimum), only as many passes as
             // the batch's index range needs.  Within a pass, element x of the
             // current order is handled in round x / NT by thread x % NT; its
-            // stable destination is the digit's offset for (round, wave) plus
-            // its rank among the wavefront's lanes with the same digit, found
-            // with 8 ballots.
+            // stable destination is the offset of (digit, round, wavefront)
+            // plus its rank among the wavefront's lanes with the same digit,
+            // found with 8 ballots.  Counts (uint8) and offsets (uint16) are
+            // stored per digit contiguously, so the thread owning a digit
+            // scans them with word accesses and clears the counts for the
+            // next pass.
             uint16_t *s_pos0 = (uint16_t *)(smem + L.pairs);
             uint16_t *s_pos1 = s_pos0 + A.max_idx;
-            uint16_t *s_cnt = (uint16_t *)(smem + L.sv);   // free until shading
             constexpr uint32_t NW = NT / kWave;
+            constexpr uint32_t DP = NT >= 256 ? 1u : 256u / NT;   // digits per thread in the scan
             const uint32_t R = (n + NT - 1) / NT;   // <= 8: the launcher sizes NT >= max_idx / 8
+            const uint32_t Gp = sort_groups(A.max_idx, NT);
+            uint32_t *s_c32 = (uint32_t *)(smem + L.sv);                       // [256][Gp] uint8 counts
+            uint2 *s_o64 = (uint2 *)(smem + L.sv + 256 * Gp);                  // [256][Gp] uint16 offsets
+            const uint16_t *s_o16 = (const uint16_t *)s_o64;
+            uint8_t *s_c8 = (uint8_t *)s_c32;
             __syncthreads();
             uint32_t kmin = kEmpty, kmax = 0;
             for (uint32_t i = tid; i < n; i += NT) {
@@ -322,53 +336,63 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
                 kmax = max(kmax, k);
                 s_pos0[i] = (uint16_t)i;
             }
-            kmin = block_reduce_min<NT>(kmin, s_tmp);
-            kmax = block_reduce_max<NT>(kmax, s_tmp);
+            for (uint32_t i = tid; i < 64 * Gp; i += NT) s_c32[i] = 0;
+            block_reduce_minmax<NT>(kmin, kmax, s_tmp);
             const uint32_t span = n ? kmax - kmin : 0u;
             const uint32_t passes = span ? (32u - __builtin_clz(span) + 7u) / 8u : 0u;
             const uint32_t w = tid / kWave;
             uint16_t *src = s_pos0, *dst = s_pos1;
             for (uint32_t pass = 0; pass < passes; ++pass) {
-                const uint32_t M = 256u * R * NW;
-                for (uint32_t i = tid; i < M; i += NT) s_cnt[i] = 0;
-                __syncthreads();
                 uint32_t dig[8], rank[8], pos[8];
-                for (uint32_t r = 0; r < R; ++r) {
-                    const uint32_t x = r * NT + tid;
-                    const bool act = x < n;
-                    const uint32_t p = act ? src[x] : 0u;
-                    const uint32_t d = act ? ((s_keys[p] - kmin) >> (8 * pass)) & 0xFFu : 0u;
-                    uint64_t peers = ballot(act);
 #pragma unroll
-                    for (int bit = 0; bit < 8; ++bit) {
-                        const uint64_t m = ballot((d >> bit) & 1u);
-                        peers &= ((d >> bit) & 1u) ? m : ~m;
+                for (uint32_t r = 0; r < 8; ++r) {
+                    if (r < R) {
+                        const uint32_t x = r * NT + tid;
+                        const bool act = x < n;
+                        const uint32_t p = act ? src[x] : 0u;
+                        const uint32_t d = act ? ((s_keys[p] - kmin) >> (8 * pass)) & 0xFFu : 0u;
+                        uint64_t peers = ballot(act);
+#pragma unroll
+                        for (int bit = 0; bit < 8; ++bit) {
+                            const uint64_t m = ballot((d >> bit) & 1u);
+                            peers &= ((d >> bit) & 1u) ? m : ~m;
+                        }
+                        const uint32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+                        if (act && rk == 0) s_c8[d * Gp + r * NW + w] = (uint8_t)__popcll(peers);
+                        dig[r] = d;
+                        rank[r] = rk;
+                        pos[r] = p;
                     }
-                    const uint32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
-                    if (act && rk == 0) s_cnt[(d * R + r) * NW + w] = (uint16_t)__popcll(peers);
-                    dig[r] = d;
-                    rank[r] = rk;
-                    pos[r] = p;
                 }
                 __syncthreads();
-                {   // exclusive scan of the counts in (digit, round, wave) order
-                    const uint32_t E = (M + NT - 1) / NT;
-                    const uint32_t lo = min(M, tid * E), hi = min(M, lo + E);
+                {   // exclusive offsets in (digit, round, wavefront) order
+                    const uint32_t d0 = tid * DP, words = Gp / 4;
                     uint32_t sum = 0;
-                    for (uint32_t i = lo; i < hi; ++i) sum += s_cnt[i];
+                    if (d0 < 256)
+                        for (uint32_t j = 0; j < DP * words; ++j) {
+                            const uint32_t c = s_c32[d0 * words + j];
+                            sum += (c & 0xFFu) + ((c >> 8) & 0xFFu) + ((c >> 16) & 0xFFu) + (c >> 24);
+                        }
                     uint32_t total;
                     uint32_t run = block_excl_scan<NT>(sum, s_tmp, total);
-                    for (uint32_t i = lo; i < hi; ++i) {
-                        const uint32_t c = s_cnt[i];
-                        s_cnt[i] = (uint16_t)run;
-                        run += c;
-                    }
+                    if (d0 < 256)
+                        for (uint32_t j = 0; j < DP * words; ++j) {
+                            const uint32_t c = s_c32[d0 * words + j];
+                            s_c32[d0 * words + j] = 0;   // counts start at zero next pass
+                            const uint32_t o0 = run, o1 = o0 + (c & 0xFFu), o2 = o1 + ((c >> 8) & 0xFFu),
+                                           o3 = o2 + ((c >> 16) & 0xFFu);
+                            run = o3 + (c >> 24);
+                            s_o64[d0 * words + j] = make_uint2(o0 | (o1 << 16), o2 | (o3 << 16));
+                        }
                 }
                 __syncthreads();
-                for (uint32_t r = 0; r < R; ++r) {
-                    const uint32_t x = r * NT + tid;
-                    if (x < n) dst[s_cnt[(dig[r] * R + r) * NW + w] + rank[r]] = (uint16_t)pos[r];
+#pragma unroll
+                for (uint32_t r = 0; r < 8; ++r) {
+                    if (r < R) {
+                        const uint32_t x = r * NT + tid;
+                        if (x < n) dst[s_o16[dig[r] * Gp + r * NW + w] + rank[r]] = (uint16_t)pos[r];
+                    }
                 }
                 __syncthreads();
                 uint16_t *t = src;
@@ -532,17 +556,31 @@ struct RoundState {
     uint32_t fill;    // lanes in use (= invocations of the round)
 };
 
-// Processes one round starting at triangle `cur`; returns the round's end.
-// When s_map is not NULL it receives each corner's lane (local id).
-__device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t cur, uint32_t t1,
-                                                 uint8_t *s_map, RoundState &st) {
+// Indices of a batch a wavefront keeps in LDS (the rest, for batches of more
+// than 256 triangles, is fetched per group of 21 triangles).
+constexpr uint32_t kBallotPrefetch = 768;
+
+// LDS of one ballot wavefront: 64 shaded vertices, the prefetched indices,
+// and a lane number per corner.
+__host__ __device__ inline uint32_t ballot_lds_bytes(uint32_t batch_tris) {
+    const uint32_t pre = 3 * batch_tris < kBallotPrefetch ? 3 * batch_tris : kBallotPrefetch;
+    return 64 * 48 + 4 * pre + ((3 * batch_tris + 15u) & ~15u);
+}
+
+// Processes one round starting at triangle `cur` of the batch starting at
+// t0; returns the round's end.  The batch's first `pre` indices are in
+// s_keys.  When s_map is not NULL it receives each corner's lane (local id).
+__device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t t0, uint32_t cur, uint32_t t1,
+                                                 const uint32_t *s_keys, uint32_t pre, uint8_t *s_map,
+                                                 RoundState &st) {
     const uint32_t lane = lane_id();
     uint32_t my_id = kEmpty, my_intro = kEmpty, fill = 0, done = 0;
     for (;;) {
         const uint32_t gt = min(21u, t1 - cur);
         const uint32_t nc = 3 * gt;
         const bool act = lane < nc;
-        const uint32_t k = act ? fetch_index(A, 3ull * cur + lane) : kEmpty;
+        const uint32_t pos = 3 * (cur - t0) + lane;
+        const uint32_t k = act ? (pos < pre ? s_keys[pos] : fetch_index(A, 3ull * cur + lane)) : kEmpty;
         uint64_t pend = ballot(act);
         uint32_t slot = 0, f = fill;
         while (pend) {
@@ -583,13 +621,13 @@ __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t cur
     return cur;
 }
 
-// One batch processed by one wavefront; s_sv (64 x 3 float4) and s_map
-// (3 * batch_tris bytes) are private to the wavefront.  Only wavefront-level
-// synchronisation is used, so several wavefronts of a workgroup can work on
-// different batches.
+// One batch processed by one wavefront in its private LDS area of
+// ballot_lds_bytes(batch_tris) bytes.  The batch's indices are loaded once,
+// up front; only wavefront-level synchronisation is used, so several
+// wavefronts of a workgroup can work on different batches.
 template <int KIND>
 __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_params &sh, uint32_t b, uint32_t nb,
-                                             f4 *s_sv, uint8_t *s_map) {
+                                             unsigned char *lds) {
     const uint32_t lane = lane_id();
     uint32_t t0, t1;
     batch_range(A, b, t0, t1);
@@ -597,6 +635,13 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
         if (lane == 0) raise_error(A.err, VR_ERR_CAPACITY);
         t1 = t0;
     }
+    const uint32_t cap = A.max_idx < kBallotPrefetch ? A.max_idx : kBallotPrefetch;
+    f4 *s_sv = (f4 *)lds;
+    uint32_t *s_keys = (uint32_t *)(lds + 64 * 48);
+    uint8_t *s_map = lds + 64 * 48 + 4 * cap;
+    const uint32_t pre = min(3 * (t1 - t0), cap);
+    for (uint32_t i = lane; i < pre; i += kWave) s_keys[i] = fetch_index(A, 3ull * t0 + i);
+    wave_sync_lds();
     uint32_t vbase = 0, ubase = b;
     RoundState st;
     if (A.need_prefix) {
@@ -604,7 +649,7 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
         // before any output so later batches can resolve their prefix
         uint32_t rounds = 0, inv = 0;
         for (uint32_t cur = t0; cur < t1; ++rounds) {
-            cur = ballot_round(A, cur, t1, nullptr, st);
+            cur = ballot_round(A, t0, cur, t1, s_keys, pre, nullptr, st);
             inv += st.fill;
         }
         uint64_t ex = 0;
@@ -618,7 +663,7 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
     }
     uint32_t r = 0, inv = 0;
     for (uint32_t cur = t0; cur < t1; ++r) {
-        const uint32_t end = ballot_round(A, cur, t1, s_map, st);
+        const uint32_t end = ballot_round(A, t0, cur, t1, s_keys, pre, s_map, st);
         if (lane < st.fill) shade_to_lds<KIND>(A, sh, st.my_id, s_sv + 3 * lane);
         wave_sync_lds();
         write_unit<64>(A, cur, end - cur, s_map, s_sv, st.fill, vbase, ubase + r, lane);
@@ -636,7 +681,7 @@ __global__ __launch_bounds__(64) void k_ballot(DrawArgs A, vr_shader_params sh) 
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const uint32_t nb = launch_units(A, batch_count(A));
     if (blockIdx.x >= nb) return;
-    ballot_batch<KIND>(A, sh, blockIdx.x, nb, (f4 *)smem, smem + 64 * 48);
+    ballot_batch<KIND>(A, sh, blockIdx.x, nb, smem);
 }
 
 }  // namespace vr

@@ -46,15 +46,89 @@ struct PlanArgs {
     uint32_t seg_len, nseg;    // L and the number of segments
     uint32_t *next;            // [T]
     uint32_t *err;
+    uint32_t *fail;            // holds `epoch` once an aligned window is over budget
+    uint32_t epoch;            // this planning call's number (never 0)
 };
+
+// True when the aligned chain of this call was verified (the general
+// kernels then have nothing to do).
+__device__ __forceinline__ bool plan_is_aligned(const uint32_t *fail, uint32_t epoch) { return *fail != epoch; }
 
 __device__ __forceinline__ uint32_t seg_lo(const PlanArgs &P, uint32_t s) { return s * P.seg_len; }
 __device__ __forceinline__ uint32_t seg_hi(const PlanArgs &P, uint32_t s) { return min(P.T, (s + 1) * P.seg_len); }
 
 // ---------------------------------------------------------------------------
+// 0. Aligned fast path.  If every aligned window [k N_pmax, (k+1) N_pmax)
+// holds at most N_u distinct indices, the greedy chain is 0, N_pmax,
+// 2 N_pmax, ...: from a start k N_pmax every prefix of the window stays
+// within the budget, so the batch takes all N_pmax triangles (or the rest of
+// the stream).  One workgroup per window counts its distinct indices in an
+// LDS hash set; a window over the budget stores the call's epoch in *fail
+// (every writer stores the same value).  Indices >= V raise
+// VR_ERR_INDEX_RANGE here, since the general pass may not run.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kCheckBits = 11;                             // 2048 slots >= 3 * N_pmax
+constexpr uint32_t kCheckPer = 3 * VR_MAX_BATCH_DYNAMIC / 256;  // corners per thread
+static_assert((1u << kCheckBits) >= 3 * VR_MAX_BATCH_DYNAMIC, "check table must hold every corner");
+
+__global__ __launch_bounds__(256) void k_plan_check(PlanArgs P) {
+    __shared__ uint32_t s_tab[1u << kCheckBits];
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t t0 = blockIdx.x * P.tmax, t1 = min(P.T, t0 + P.tmax);
+    const uint32_t n = 3 * (t1 - t0);
+    uint32_t key[kCheckPer];
+#pragma unroll
+    for (uint32_t k = 0; k < kCheckPer; ++k) {
+        const uint32_t i = tid + 256 * k;
+        uint32_t v = i < n ? P.idx[3ull * t0 + i] : 0u;
+        if (i < n && v >= P.V) {
+            raise_error(P.err, VR_ERR_INDEX_RANGE);
+            v = 0;
+        }
+        key[k] = v;
+    }
+    for (uint32_t q = tid; q < (1u << kCheckBits); q += 256) s_tab[q] = kEmpty;
+    __syncthreads();
+    uint32_t slot[kCheckPer], pending = 0, fresh = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kCheckPer; ++k) {
+        slot[k] = hash_slot(key[k], kCheckBits);
+        if (tid + 256 * k < n) pending |= 1u << k;
+    }
+    while (pending) {   // lockstep linear probing; the table never fills
+#pragma unroll
+        for (uint32_t k = 0; k < kCheckPer; ++k) {
+            if (pending & (1u << k)) {
+                const uint32_t prev = atomicCAS(&s_tab[slot[k]], kEmpty, key[k]);
+                if (prev == kEmpty || prev == key[k]) {
+                    fresh += prev == kEmpty;
+                    pending &= ~(1u << k);
+                } else {
+                    slot[k] = (slot[k] + 1) & ((1u << kCheckBits) - 1);
+                }
+            }
+        }
+    }
+    uint32_t distinct;
+    block_excl_scan<256>(fresh, s_tmp, distinct);
+    if (tid == 0 && distinct > P.cap) *P.fail = P.epoch;
+}
+
+// Writes the aligned chain [K, 0, N_pmax, .., (K-1) N_pmax, T] when it was
+// verified.
+__global__ __launch_bounds__(256) void k_plan_aligned(PlanArgs P, uint32_t *plan) {
+    if (!plan_is_aligned(P.fail, P.epoch)) return;
+    const uint32_t K = (P.T + P.tmax - 1) / P.tmax;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < K + 2; i += gridDim.x * 256)
+        plan[i] = i == 0 ? K : (i == K + 1 ? P.T : (i - 1) * P.tmax);
+}
+
+// ---------------------------------------------------------------------------
 // 1. next(c) for every start c
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
+    if (plan_is_aligned(P.fail, P.epoch)) return;
     // LDS regions are reused once their first contents are dead:
     //   s_a: indices (insert) -> corner positions grouped by slot + start counts
     //   s_tab: keys (insert) -> bucket starts | bucket ends (2 x uint16)
@@ -240,6 +314,7 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_plan_table(PlanArgs P, uint16_t *tab) {
     extern __shared__ uint32_t s_ptr[];   // seg_len entries
+    if (plan_is_aligned(P.fail, P.epoch)) return;
     constexpr uint32_t kDone = 0x80000000u;
     const uint32_t s = blockIdx.x;
     const uint32_t b = seg_lo(P, s), e = seg_hi(P, s), len = e - b;
@@ -272,8 +347,9 @@ __global__ __launch_bounds__(256) void k_plan_table(PlanArgs P, uint16_t *tab) {
 // Composes tables [g*kFanIn, min(count, g*kFanIn + kFanIn)) of `in` into
 // table g of `out`.
 __global__ __launch_bounds__(512) void k_plan_compose(uint32_t tmax, uint32_t count, const uint16_t *in,
-                                                      uint16_t *out) {
+                                                      uint16_t *out, const uint32_t *fail, uint32_t epoch) {
     extern __shared__ uint16_t s_t[];   // kFanIn * tmax
+    if (plan_is_aligned(fail, epoch)) return;
     const uint32_t g = blockIdx.x;
     const uint32_t k0 = g * kFanIn, k1 = min(count, k0 + kFanIn);
     const uint32_t m = (k1 - k0) * tmax;
@@ -289,8 +365,9 @@ __global__ __launch_bounds__(512) void k_plan_compose(uint32_t tmax, uint32_t co
 // One workgroup: applies the (at most kFanIn) top tables in order starting
 // from entry 0 and records each table's entry.
 __global__ __launch_bounds__(256) void k_plan_top(uint32_t tmax, uint32_t count, const uint16_t *tab,
-                                                  uint16_t *entry) {
+                                                  uint16_t *entry, const uint32_t *fail, uint32_t epoch) {
     extern __shared__ uint16_t s_t[];
+    if (plan_is_aligned(fail, epoch)) return;
     const uint32_t m = count * tmax;
     for (uint32_t i = threadIdx.x; i < m; i += 256) s_t[i] = tab[i];
     __syncthreads();
@@ -306,8 +383,10 @@ __global__ __launch_bounds__(256) void k_plan_top(uint32_t tmax, uint32_t count,
 // Pushes entries one level down: group g of `tab` (kFanIn tables) receives
 // its entry from up_entry[g] and records its members' entries.
 __global__ __launch_bounds__(256) void k_plan_resolve(uint32_t tmax, uint32_t count, const uint16_t *tab,
-                                                      const uint16_t *up_entry, uint16_t *entry) {
+                                                      const uint16_t *up_entry, uint16_t *entry,
+                                                      const uint32_t *fail, uint32_t epoch) {
     extern __shared__ uint16_t s_t[];
+    if (plan_is_aligned(fail, epoch)) return;
     const uint32_t g = blockIdx.x;
     const uint32_t k0 = g * kFanIn, k1 = min(count, k0 + kFanIn);
     const uint32_t m = (k1 - k0) * tmax;
@@ -326,6 +405,7 @@ __global__ __launch_bounds__(256) void k_plan_resolve(uint32_t tmax, uint32_t co
 __global__ __launch_bounds__(64) void k_plan_emit(PlanArgs P, const uint16_t *entry, uint32_t *cuts,
                                                   uint32_t *ncuts) {
     extern __shared__ uint32_t s_next[];   // seg_len entries
+    if (plan_is_aligned(P.fail, P.epoch)) return;
     const uint32_t s = blockIdx.x;
     const uint32_t b = seg_lo(P, s), e = seg_hi(P, s);
     for (uint32_t i = threadIdx.x; i < e - b; i += 64) s_next[i] = P.next[b + i];
@@ -347,6 +427,7 @@ constexpr uint32_t kPackSegs = 4096;
 
 __global__ __launch_bounds__(64) void k_plan_pack_seg(PlanArgs P, const uint32_t *cuts, const uint32_t *ncuts,
                                                       uint32_t *plan) {
+    if (plan_is_aligned(P.fail, P.epoch)) return;
     const uint32_t s = blockIdx.x;
     uint32_t sum = 0;
     for (uint32_t j = lane_id(); j < s; j += kWave) sum += ncuts[j];
@@ -365,6 +446,7 @@ __global__ __launch_bounds__(64) void k_plan_pack_seg(PlanArgs P, const uint32_t
 __global__ __launch_bounds__(1024) void k_plan_pack(PlanArgs P, const uint32_t *cuts, uint32_t *ncuts,
                                                     uint32_t *plan) {
     __shared__ uint32_t tmp[16];
+    if (plan_is_aligned(P.fail, P.epoch)) return;
     const uint32_t E = (P.nseg + 1023) / 1024;
     const uint32_t lo = min(P.nseg, threadIdx.x * E), hi = min(P.nseg, lo + E);
     uint32_t sum = 0;

@@ -33,7 +33,7 @@ thread_local std::string g_create_error;
 // since the last vr_sync.
 struct CtxWords {
     uint32_t err;
-    uint32_t pad;
+    uint32_t plan_fail;   // epoch of the last planning call whose aligned chain failed
     unsigned long long total_inv;
 };
 
@@ -53,6 +53,7 @@ struct vr_ctx {
     CtxWords *d_words = nullptr;
     Scratch status, agg, plan, plan_work, tune;
     uint32_t host_err = 0;   // data error found on the host, reported by vr_sync
+    uint32_t plan_epoch = 0;  // numbers planning calls (0 is never used)
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;   // reused event pairs
     size_t ev_used = 0;
@@ -318,25 +319,33 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     P.nseg = nseg;
     P.next = next;
     P.err = &c->d_words->err;
+    P.fail = &c->d_words->plan_fail;
+    if (++c->plan_epoch == 0) c->plan_epoch = 1;
+    P.epoch = c->plan_epoch;
     TimedRegion timed(c);
+    const uint32_t K = (T + tmax - 1) / tmax;
+    hipLaunchKernelGGL(k_plan_check, dim3(K), dim3(256), 0, c->stream, P);
     hipLaunchKernelGGL(k_plan_next, dim3((T + kNextBlock - 1) / kNextBlock), dim3(256), 0, c->stream, P);
     hipLaunchKernelGGL(k_plan_table, dim3(nseg), dim3(256), 4 * L, c->stream, P, tab(0));
     const uint32_t grp_lds = 2 * kFanIn * tmax;
     for (size_t l = 0; l + 1 < counts.size(); ++l)
         hipLaunchKernelGGL(k_plan_compose, dim3(counts[l + 1]), dim3(512), grp_lds, c->stream, tmax, counts[l],
-                           (const uint16_t *)tab(l), tab(l + 1));
+                           (const uint16_t *)tab(l), tab(l + 1), (const uint32_t *)P.fail, P.epoch);
     const size_t top = counts.size() - 1;
     hipLaunchKernelGGL(k_plan_top, dim3(1), dim3(256), 2 * counts[top] * tmax, c->stream, tmax, counts[top],
-                       (const uint16_t *)tab(top), ent(top));
+                       (const uint16_t *)tab(top), ent(top), (const uint32_t *)P.fail, P.epoch);
     for (size_t l = top; l-- > 0;)
         hipLaunchKernelGGL(k_plan_resolve, dim3(counts[l + 1]), dim3(256), grp_lds, c->stream, tmax, counts[l],
-                           (const uint16_t *)tab(l), (const uint16_t *)ent(l + 1), ent(l));
+                           (const uint16_t *)tab(l), (const uint16_t *)ent(l + 1), ent(l), (const uint32_t *)P.fail,
+                           P.epoch);
     hipLaunchKernelGGL(k_plan_emit, dim3(nseg), dim3(64), 4 * L, c->stream, P, (const uint16_t *)ent(0), cuts, ncuts);
     if (nseg <= kPackSegs)
         hipLaunchKernelGGL(k_plan_pack_seg, dim3(nseg), dim3(64), 0, c->stream, P, (const uint32_t *)cuts,
                            (const uint32_t *)ncuts, d_plan);
     else
         hipLaunchKernelGGL(k_plan_pack, dim3(1), dim3(1024), 0, c->stream, P, (const uint32_t *)cuts, ncuts, d_plan);
+    hipLaunchKernelGGL(k_plan_aligned, dim3(std::min<uint32_t>(1024, (K + 2 + 255) / 256)), dim3(256), 0, c->stream, P,
+                       d_plan);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
 }
@@ -459,10 +468,10 @@ vr_status describe_draw(vr_ctx *c, const vr_draw &D, const vr_shader_params &sh,
         need.slots += nb;
         if (X.mode == kFrameBallot) {
             need.units += (nb + 3) / 4;
-            need.ballot_stride = std::max(need.ballot_stride, align16(64 * 48 + 3 * D.batch_tris));
+            need.ballot_stride = std::max(need.ballot_stride, align16(ballot_lds_bytes(D.batch_tris)));
         } else {
             need.units += nb;
-            need.unit_lds = std::max(need.unit_lds, dedup_lds_layout((int)X.mode, r.max_idx, r.max_uniq, r.hash_bits).total);
+            need.unit_lds = std::max(need.unit_lds, dedup_lds_layout((int)X.mode, r.max_idx, r.max_uniq, r.hash_bits, kFrameNT).total);
         }
     }
     return VR_OK;
@@ -633,7 +642,7 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
     }
     TimedRegion timed(c);
     if (is_ballot(strategy)) {
-        const uint32_t lds = 64 * 48 + ((3 * batch_tris + 15) & ~15u);
+        const uint32_t lds = ballot_lds_bytes(batch_tris);
         if (sh.kind == 0) launch_ballot<0>(c, A, sh, lds, nb_bound);
         else if (sh.kind == 1) launch_ballot<1>(c, A, sh, lds, nb_bound);
         else launch_ballot<2>(c, A, sh, lds, nb_bound);
@@ -641,7 +650,7 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
         const int mode = (strategy == VR_STATIC_SORT || strategy == VR_DYN_SORT) ? kSort
                          : (strategy == VR_DYN_PHASH)                             ? kPHash
                                                                                   : kHash;
-        const uint32_t lds = dedup_lds_layout(mode, r.max_idx, r.max_uniq, r.hash_bits).total;
+        const uint32_t lds = dedup_lds_layout(mode, r.max_idx, r.max_uniq, r.hash_bits, r.nt).total;
         if (lds > c->lds_limit)
             return fail(c, VR_ERR_ARG, "LDS need %u B exceeds the %zu B limit (lower hash_slots or batch_tris)", lds,
                         c->lds_limit);

@@ -141,8 +141,11 @@ def test_parity_corners_only_mode(stage):
 @pytest.mark.parametrize("nu,tmax", [(3, 5), (64, 85), (256, 341), (512, 512), (100, 33), (7, 512)])
 def test_plan_parity(stage, nu, tmax):
     from paper_1805_08893_amd import vr
+    ordered = W.grid_mesh(120, 90, 8, "hilbert")
+    mixed = W.Mesh("hilbert_then_random",
+                   np.concatenate([ordered.indices, W.grid_mesh(120, 90, 8, "random").indices]), ordered.vertices)
     for mesh in (W.icosphere_mesh(6, 8, "hilbert", swap_frac=0.05), W.grid_mesh(160, 150, 8, "random"),
-                 W.grid_mesh(97, 31, 8, "scan")):
+                 W.grid_mesh(97, 31, 8, "scan"), mixed):
         _log(f"case plan nu={nu} tmax={tmax} mesh={mesh.name} T={mesh.num_tris}")
         exp = vro.plan_dynamic(mesh.indices, mesh.num_verts, nu, tmax)
         idx = _dev(mesh.indices)

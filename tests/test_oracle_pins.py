@@ -409,3 +409,21 @@ def test_plan_of_a_prefix_is_the_cut_plan():
                 starts = full[:-1]
                 cut = np.concatenate([starts[starts < Tp], [Tp]]).astype(np.uint32)
                 assert np.array_equal(own, cut), (m.name, nu, bt, Tp)
+
+
+def test_plan_is_the_aligned_chain_when_every_window_fits():
+    """If every aligned window of N_pmax triangles holds at most N_u distinct
+    indices, greedy batching cuts exactly at multiples of N_pmax (every
+    prefix of such a window also fits).  The device planner takes this as a
+    fast path after checking the windows."""
+    cases = 0
+    for m in (W.grid_mesh(40, 30, 2, "hilbert"), W.icosphere_mesh(4, 3, "hilbert"), W.grid_mesh(50, 20, 4, "scan")):
+        T = m.num_tris
+        for nu, bt in ((256, 256), (64, 21), (100, 33), (512, 341), (40, 16)):
+            fits = all(len(np.unique(m.indices[3 * t:3 * min(T, t + bt)])) <= nu for t in range(0, T, bt))
+            plan = vro.plan_dynamic(m.indices, m.num_verts, nu, bt)
+            aligned = np.concatenate([np.arange(0, T, bt), [T]]).astype(np.uint32)
+            if fits:
+                cases += 1
+                assert np.array_equal(plan, aligned), (m.name, nu, bt)
+    assert cases >= 8
