@@ -164,6 +164,57 @@ def scene_benchmark(stage, seed=3, num_draws=2000, replays=10):
             "invocations_per_draw": inv_loop, "autotune_and_plan_s": t_tune, "classes": classes}
 
 
+def sweep(mesh, sp, reps=10):
+    """Batch-size sweep of every strategy (one JSON line per configuration):
+    main-kernel time, plan time and invocations."""
+    import torch
+    from paper_1805_08893_amd import vr
+    T, V = mesh.num_tris, mesh.num_verts
+    idx = torch.from_numpy(mesh.indices.view(np.int32)).cuda()
+    vtx = torch.from_numpy(mesh.vertices).cuda()
+    stage = vr.GeometryStage(0)
+    shader = vr.make_shader(sp)
+    plan = torch.empty(T + 2, dtype=torch.int32, device="cuda")
+    out = stage.alloc_outputs(T, vr.VR_NAIVE, 1, corners=True)
+    configs = [("naive", vr.VR_NAIVE, 1, 0)]
+    for bt in (21, 32, 64, 128, 256, 512, 1024):
+        configs.append(("static_ballot", vr.VR_STATIC_BALLOT, bt, 0))
+    for bt in (32, 64, 128, 256):
+        configs += [("static_sort", vr.VR_STATIC_SORT, bt, 0), ("static_hash", vr.VR_STATIC_HASH, bt, 0)]
+    for nu, bt in ((64, 64), (128, 128), (256, 128), (256, 256), (256, 341), (512, 512)):
+        for name, s in (("dyn_ballot", vr.VR_DYN_BALLOT), ("dyn_sort", vr.VR_DYN_SORT), ("dyn_hash", vr.VR_DYN_HASH),
+                        ("dyn_phash", vr.VR_DYN_PHASH)):
+            configs.append((name, s, bt, nu))
+    for name, s, bt, nu in configs:
+        plan_ms = None
+        if s in vr.DYNAMIC:
+            vr.vr_set_kernel_timing(stage.ctx, True)
+            vr.vr_kernel_times(stage.ctx)
+            for _ in range(reps):
+                stage.check(vr.vr_plan_dynamic(stage.ctx, idx, V, nu, bt, plan))
+            plan_ms = float(np.mean(vr.vr_kernel_times(stage.ctx)))
+        o = vr.make_opts(max_unique=nu, plan=plan if s in vr.DYNAMIC else None)
+        rc = vr.vr_check_args(3 * T, V, shader, s, bt, o, stage.describe(out))
+        if rc != vr.VR_OK:
+            print(json.dumps({"strategy": name, "batch_tris": bt, "max_unique": nu, "error": rc}), flush=True)
+            continue
+        for _ in range(2):
+            stage.check(vr.vr_process_draw(stage.ctx, idx, vtx, shader, s, bt, o, stage.describe(out)))
+        vr.vr_set_kernel_timing(stage.ctx, True)
+        vr.vr_kernel_times(stage.ctx)
+        for _ in range(reps):
+            stage.check(vr.vr_process_draw(stage.ctx, idx, vtx, shader, s, bt, o, stage.describe(out)))
+        ms = float(np.mean(vr.vr_kernel_times(stage.ctx)))
+        vr.vr_set_kernel_timing(stage.ctx, False)
+        st, inv = stage.sync()
+        stage.check(st)
+        inv //= reps + 2
+        print(json.dumps({"strategy": name, "batch_tris": bt, "max_unique": nu, "kernel_us": round(ms * 1e3, 1),
+                          "plan_us": None if plan_ms is None else round(plan_ms * 1e3, 1), "invocations": inv,
+                          "reuse": round(1 - inv / (3 * T), 4), "tri_per_s": T / (ms * 1e-3)}), flush=True)
+    stage.close()
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -240,6 +291,8 @@ def main():
     ap.add_argument("--only", default=None, help="run only this strategy in each step (profiling)")
     ap.add_argument("--no-scene", action="store_true", help="skip the many-draw frame measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time every strategy over batch sizes 32..1024 on the workload and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="time a plain device-to-device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -274,6 +327,9 @@ def main():
         return
     mesh, sp = W.icosphere8_hilbert_phong8(level=args.level)
     T, V = mesh.num_tris, mesh.num_verts
+    if args.sweep:
+        sweep(mesh, sp, reps=max(3, args.steps))
+        return
     U = int(len(np.unique(mesh.indices)))
     idx = torch.from_numpy(mesh.indices.view(np.int32)).cuda()
     vtx = torch.from_numpy(mesh.vertices).cuda()
@@ -313,20 +369,29 @@ def main():
     st, _ = stage.sync()
     stage.check(st)
 
+    # the timed steps: nothing but the work of the step on the stream
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st, inv_total = stage.sync()
+    stage.check(st)
+
+    # the same steps again, instrumented: HIP events around every draw and
+    # around every main kernel (breakdown and roofline only)
     names = ["plan"] + [s[0] for s in strategies]
     ev = [{n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for n in names}
           for _ in range(args.steps)]
     vr.vr_set_kernel_timing(stage.ctx, True)
     vr.vr_kernel_times(stage.ctx)           # start from an empty record
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for k in range(args.steps):
         step(ev[k])
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     ktimes = np.array(vr.vr_kernel_times(stage.ctx), dtype=np.float64).reshape(args.steps, len(names))
     vr.vr_set_kernel_timing(stage.ctx, False)
-    st, inv_total = stage.sync()
+    st, _ = stage.sync()
     stage.check(st)
 
     ms_step = (t1 - t0) * 1e3 / args.steps

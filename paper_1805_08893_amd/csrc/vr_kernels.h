@@ -560,19 +560,30 @@ struct RoundState {
 // than 256 triangles, is fetched per group of 21 triangles).
 constexpr uint32_t kBallotPrefetch = 768;
 
-// LDS of one ballot wavefront: 64 shaded vertices, the prefetched indices,
-// and a lane number per corner.
+// LDS of one ballot wavefront: 64 shaded vertices, the prefetched indices, a
+// hand-over area for new values (2 x 64 words) and a lane number per corner.
 __host__ __device__ inline uint32_t ballot_lds_bytes(uint32_t batch_tris) {
     const uint32_t pre = 3 * batch_tris < kBallotPrefetch ? 3 * batch_tris : kBallotPrefetch;
-    return 64 * 48 + 4 * pre + ((3 * batch_tris + 15u) & ~15u);
+    return 64 * 48 + 4 * pre + 2 * 64 * 4 + ((3 * batch_tris + 15u) & ~15u);
 }
 
 // Processes one round starting at triangle `cur` of the batch starting at
 // t0; returns the round's end.  The batch's first `pre` indices are in
-// s_keys.  When s_map is not NULL it receives each corner's lane (local id).
+// s_keys; s_new is the wavefront's hand-over area.  When s_map is not NULL
+// it receives each corner's lane (local id).
+//
+// A group of 21 triangles is resolved by votes: each step takes four
+// pending lanes (lowest, highest, second lowest, second highest), broadcasts
+// their indices and ballots the lanes holding each of them and the lane that
+// already owns it.  Every lane learns the first lane of its value; values no
+// lane owns get the next free lanes in the order of their first lanes (a
+// popcount of the first lanes below), and the first lane hands the value to
+// the lane of its slot through LDS.  This is the sequential assignment of
+// Algorithm 1 (lowest unresolved lane first), with up to four distinct values
+// resolved per step.
 __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t t0, uint32_t cur, uint32_t t1,
-                                                 const uint32_t *s_keys, uint32_t pre, uint8_t *s_map,
-                                                 RoundState &st) {
+                                                 const uint32_t *s_keys, uint32_t pre, uint32_t *s_new,
+                                                 uint8_t *s_map, RoundState &st) {
     const uint32_t lane = lane_id();
     uint32_t my_id = kEmpty, my_intro = kEmpty, fill = 0, done = 0;
     for (;;) {
@@ -581,26 +592,42 @@ __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t t0,
         const bool act = lane < nc;
         const uint32_t pos = 3 * (cur - t0) + lane;
         const uint32_t k = act ? (pos < pre ? s_keys[pos] : fetch_index(A, 3ull * cur + lane)) : kEmpty;
-        uint64_t pend = ballot(act);
-        uint32_t slot = 0, f = fill;
+        uint64_t pend = ballot(act), fresh = 0;
+        uint32_t first = lane, owner = kEmpty;
         while (pend) {
-            const uint32_t i = (uint32_t)__ffsll((long long)pend) - 1;
-            const uint32_t cv = __builtin_amdgcn_readlane(k, i);
-            const uint64_t same = ballot(k == cv) & pend;
-            const uint64_t own = ballot(my_id == cv);
-            uint32_t s;
-            if (own) {
-                s = (uint32_t)__ffsll((long long)own) - 1;
-            } else {
-                s = f;
-                if (lane == f) {
-                    my_id = cv;
-                    my_intro = done + i;
+            const uint32_t ia = (uint32_t)__ffsll((long long)pend) - 1;
+            const uint32_t ib = 63u - (uint32_t)__clzll((long long)pend);
+            const uint64_t rest = pend & ~(1ull << ia) & ~(1ull << ib);
+            const uint32_t ic = rest ? (uint32_t)__ffsll((long long)rest) - 1 : ia;
+            const uint32_t id = rest ? 63u - (uint32_t)__clzll((long long)rest) : ib;
+            const uint32_t pick[4] = {ia, ib, ic, id};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {   // values may coincide: the updates are idempotent
+                const uint32_t cv = __builtin_amdgcn_readlane(k, pick[j]);
+                const uint64_t same = ballot(k == cv);
+                const uint64_t own = ballot(my_id == cv);
+                const bool mine = (same >> lane) & 1ull;
+                if (own) {
+                    if (mine) owner = (uint32_t)__ffsll((long long)own) - 1;
+                } else {
+                    const uint32_t fl = (uint32_t)__ffsll((long long)same) - 1;
+                    if (mine) first = fl;
+                    fresh |= 1ull << fl;
                 }
-                ++f;
+                pend &= ~same;
             }
-            if ((same >> lane) & 1ull) slot = s;
-            pend &= ~same;
+        }
+        const uint32_t slot = owner != kEmpty ? owner
+                                              : fill + (uint32_t)__popcll(fresh & ((1ull << first) - 1ull));
+        if (act && owner == kEmpty && first == lane && slot < (uint32_t)kWave) {
+            s_new[slot] = k;
+            s_new[kWave + slot] = done + lane;
+        }
+        wave_sync_lds();
+        const uint32_t f = fill + (uint32_t)__popcll(fresh);
+        if (lane >= fill && lane < f) {
+            my_id = s_new[lane];
+            my_intro = s_new[kWave + lane];
         }
         const uint64_t bad = ballot(act && slot >= (uint32_t)kWave);
         const uint32_t acc = bad ? ((uint32_t)__ffsll((long long)bad) - 1) / 3 : gt;
@@ -638,7 +665,8 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
     const uint32_t cap = A.max_idx < kBallotPrefetch ? A.max_idx : kBallotPrefetch;
     f4 *s_sv = (f4 *)lds;
     uint32_t *s_keys = (uint32_t *)(lds + 64 * 48);
-    uint8_t *s_map = lds + 64 * 48 + 4 * cap;
+    uint32_t *s_new = s_keys + cap;
+    uint8_t *s_map = (uint8_t *)(s_new + 2 * kWave);
     const uint32_t pre = min(3 * (t1 - t0), cap);
     for (uint32_t i = lane; i < pre; i += kWave) s_keys[i] = fetch_index(A, 3ull * t0 + i);
     wave_sync_lds();
@@ -649,7 +677,7 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
         // before any output so later batches can resolve their prefix
         uint32_t rounds = 0, inv = 0;
         for (uint32_t cur = t0; cur < t1; ++rounds) {
-            cur = ballot_round(A, t0, cur, t1, s_keys, pre, nullptr, st);
+            cur = ballot_round(A, t0, cur, t1, s_keys, pre, s_new, nullptr, st);
             inv += st.fill;
         }
         uint64_t ex = 0;
@@ -663,7 +691,7 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
     }
     uint32_t r = 0, inv = 0;
     for (uint32_t cur = t0; cur < t1; ++r) {
-        const uint32_t end = ballot_round(A, t0, cur, t1, s_keys, pre, s_map, st);
+        const uint32_t end = ballot_round(A, t0, cur, t1, s_keys, pre, s_new, s_map, st);
         if (lane < st.fill) shade_to_lds<KIND>(A, sh, st.my_id, s_sv + 3 * lane);
         wave_sync_lds();
         write_unit<64>(A, cur, end - cur, s_map, s_sv, st.fill, vbase, ubase + r, lane);
@@ -676,12 +704,19 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
     if (lane == 0 && A.agg) A.agg[b] = ((unsigned long long)r << 32) | inv;
 }
 
+// Four wavefronts per workgroup, one batch each (batch 4 * workgroup +
+// wavefront); `stride` is the per-wavefront LDS area.  Larger workgroups keep
+// more wavefronts resident than one-wavefront workgroups would.
+constexpr uint32_t kBallotWaves = 4;
+
 template <int KIND>
-__global__ __launch_bounds__(64) void k_ballot(DrawArgs A, vr_shader_params sh) {
+__global__ __launch_bounds__(kBallotWaves * 64) void k_ballot(DrawArgs A, vr_shader_params sh, uint32_t stride) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const uint32_t nb = launch_units(A, batch_count(A));
-    if (blockIdx.x >= nb) return;
-    ballot_batch<KIND>(A, sh, blockIdx.x, nb, smem);
+    const uint32_t w = threadIdx.x / kWave;
+    const uint32_t b = blockIdx.x * kBallotWaves + w;
+    if (b >= nb) return;   // only wavefront-level synchronisation follows
+    ballot_batch<KIND>(A, sh, b, nb, smem + w * stride);
 }
 
 }  // namespace vr

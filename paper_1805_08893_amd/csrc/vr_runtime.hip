@@ -256,8 +256,9 @@ void dispatch_kind(vr_ctx *c, uint32_t kind, uint32_t nt, const DrawArgs &A, con
 }
 
 template <int KIND>
-void launch_ballot(vr_ctx *c, const DrawArgs &A, const vr_shader_params &sh, uint32_t lds, uint64_t batches) {
-    hipLaunchKernelGGL(k_ballot<KIND>, dim3((uint32_t)batches), dim3(64), lds, c->stream, A, sh);
+void launch_ballot(vr_ctx *c, const DrawArgs &A, const vr_shader_params &sh, uint32_t stride, uint64_t batches) {
+    hipLaunchKernelGGL(k_ballot<KIND>, dim3((uint32_t)((batches + kBallotWaves - 1) / kBallotWaves)),
+                       dim3(kBallotWaves * 64), kBallotWaves * stride, c->stream, A, sh, stride);
 }
 
 template <int KIND>
@@ -642,7 +643,7 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
     }
     TimedRegion timed(c);
     if (is_ballot(strategy)) {
-        const uint32_t lds = ballot_lds_bytes(batch_tris);
+        const uint32_t lds = align16(ballot_lds_bytes(batch_tris));   // per wavefront
         if (sh.kind == 0) launch_ballot<0>(c, A, sh, lds, nb_bound);
         else if (sh.kind == 1) launch_ballot<1>(c, A, sh, lds, nb_bound);
         else launch_ballot<2>(c, A, sh, lds, nb_bound);
