@@ -601,20 +601,30 @@ __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t t0,
             const uint32_t ic = rest ? (uint32_t)__ffsll((long long)rest) - 1 : ia;
             const uint32_t id = rest ? 63u - (uint32_t)__clzll((long long)rest) : ib;
             const uint32_t pick[4] = {ia, ib, ic, id};
+            if (fill == 0) {   // nothing owned yet in this round
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {   // values may coincide: the updates are idempotent
-                const uint32_t cv = __builtin_amdgcn_readlane(k, pick[j]);
-                const uint64_t same = ballot(k == cv);
-                const uint64_t own = ballot(my_id == cv);
-                const bool mine = (same >> lane) & 1ull;
-                if (own) {
-                    if (mine) owner = (uint32_t)__ffsll((long long)own) - 1;
-                } else {
-                    const uint32_t fl = (uint32_t)__ffsll((long long)same) - 1;
-                    if (mine) first = fl;
+                for (int j = 0; j < 4; ++j) {   // values may coincide: the updates are idempotent
+                    const uint32_t cv = __builtin_amdgcn_readlane(k, pick[j]);
+                    const uint64_t same = ballot(k == cv);   // never empty: holds pick[j]
+                    const uint32_t fl = (uint32_t)__builtin_ctzll(same);
+                    first = __builtin_amdgcn_inverse_ballot_w64(same) ? fl : first;
                     fresh |= 1ull << fl;
+                    pend &= ~same;
                 }
-                pend &= ~same;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t cv = __builtin_amdgcn_readlane(k, pick[j]);
+                    const uint64_t same = ballot(k == cv);   // never empty: holds pick[j]
+                    const uint64_t own = ballot(my_id == cv);
+                    const uint32_t fl = (uint32_t)__builtin_ctzll(same);
+                    const uint32_t ol = (uint32_t)__builtin_ctzll(own | (1ull << 63));   // used only if own
+                    const uint64_t held = own ? ~0ull : 0ull;
+                    owner = __builtin_amdgcn_inverse_ballot_w64(same & held) ? ol : owner;
+                    first = __builtin_amdgcn_inverse_ballot_w64(same & ~held) ? fl : first;
+                    fresh |= (1ull << fl) & ~held;
+                    pend &= ~same;
+                }
             }
         }
         const uint32_t slot = owner != kEmpty ? owner

@@ -32,12 +32,22 @@
 namespace vr {
 
 constexpr uint32_t kNextBlock = 256;                         // starts per workgroup
-constexpr uint32_t kNextTris = kNextBlock + VR_MAX_BATCH_DYNAMIC;
-constexpr uint32_t kNextSlots = 4096;                        // LDS hash slots (>= 3 * kNextTris)
 constexpr uint32_t kFanIn = 32;                              // tables composed per group
 constexpr uint16_t kEnd = 0xFFFF;                            // table value: the chain has ended
 constexpr uint32_t kNone = 0xFFFF;                           // no previous occurrence
-static_assert(kNextSlots >= 3 * kNextTris, "hash table must hold every staged corner");
+
+// Window of k_plan_next for primitive caps up to TM triangles: the staged
+// triangles, and a power-of-two hash table that holds every staged corner.
+template <uint32_t TM>
+struct NextWindow {
+    static constexpr uint32_t tris = kNextBlock + TM;
+    static constexpr uint32_t bits = 3 * tris <= 2048 ? 11 : 12;
+    static constexpr uint32_t slots = 1u << bits;
+    static constexpr uint32_t per = 3 * tris / 256;            // corners per thread
+    static constexpr uint32_t prev_words = (slots / 4 > tris + 4) ? slots / 4 : tris + 4;
+    static_assert(slots >= 3 * tris, "hash table must hold every staged corner");
+    static_assert((3 * tris) % 256 == 0, "corners split evenly over the threads");
+};
 
 struct PlanArgs {
     const uint32_t *idx;
@@ -127,7 +137,10 @@ __global__ __launch_bounds__(256) void k_plan_aligned(PlanArgs P, uint32_t *plan
 // ---------------------------------------------------------------------------
 // 1. next(c) for every start c
 // ---------------------------------------------------------------------------
+template <uint32_t TM>
 __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
+    using Win = NextWindow<TM>;
+    constexpr uint32_t kNextTris = Win::tris, kNextSlots = Win::slots;
     if (plan_is_aligned(P.fail, P.epoch)) return;
     // LDS regions are reused once their first contents are dead:
     //   s_a: indices (insert) -> corner positions grouped by slot + start counts
@@ -135,12 +148,10 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
     //   s_cnt: slot counts -> 3 x 16-bit previous occurrence per triangle
     __shared__ uint32_t s_a[3 * kNextTris];
     __shared__ uint32_t s_tab[kNextSlots];
-    __shared__ unsigned long long s_cntprev[kNextSlots / 4];
+    __shared__ unsigned long long s_cntprev[Win::prev_words];
     __shared__ uint32_t s_tmp[4];
-    static_assert(kNextSlots / 4 >= kNextTris + 4, "previous-occurrence table fits the count array");
     uint16_t *s_cnt = (uint16_t *)s_cntprev;
     unsigned long long *s_prev = s_cntprev;
-    static_assert((3 * kNextTris) % 256 == 0, "corners split evenly over the threads");
     uint32_t *s_key = s_a;
     uint16_t *s_arr = (uint16_t *)s_a;                       // 3 * kNextTris entries
     int *s_diff = (int *)(s_a + (3 * kNextTris + 1) / 2);    // kNextBlock + 1 entries
@@ -165,8 +176,8 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
     __syncthreads();
     // insertion: every thread owns corners tid + 256*k (k < kPer) and probes
     // them in lockstep rounds so their LDS round trips overlap
-    constexpr uint32_t kBits = 12;   // log2(kNextSlots)
-    constexpr uint32_t kPer = 3 * kNextTris / 256;
+    constexpr uint32_t kBits = Win::bits;
+    constexpr uint32_t kPer = Win::per;
     uint32_t key[kPer], slot[kPer];
     uint32_t pending = 0;
 #pragma unroll

@@ -326,7 +326,11 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     TimedRegion timed(c);
     const uint32_t K = (T + tmax - 1) / tmax;
     hipLaunchKernelGGL(k_plan_check, dim3(K), dim3(256), 0, c->stream, P);
-    hipLaunchKernelGGL(k_plan_next, dim3((T + kNextBlock - 1) / kNextBlock), dim3(256), 0, c->stream, P);
+    if (tmax <= 256)
+        hipLaunchKernelGGL(k_plan_next<256>, dim3((T + kNextBlock - 1) / kNextBlock), dim3(256), 0, c->stream, P);
+    else
+        hipLaunchKernelGGL(k_plan_next<VR_MAX_BATCH_DYNAMIC>, dim3((T + kNextBlock - 1) / kNextBlock), dim3(256), 0,
+                           c->stream, P);
     hipLaunchKernelGGL(k_plan_table, dim3(nseg), dim3(256), 4 * L, c->stream, P, tab(0));
     const uint32_t grp_lds = 2 * kFanIn * tmax;
     for (size_t l = 0; l + 1 < counts.size(); ++l)

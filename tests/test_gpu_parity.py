@@ -248,3 +248,34 @@ def test_parity_full_icosphere8_phong8(stage, ico8, sname, strategy, bt, nu):
     rc, ora = vro.process_draw(mesh.indices, mesh.vertices, sp, strategy, bt, {"max_unique": nu})
     gpu = gpu_draw(stage, mesh, sp, strategy, bt, nu)
     compare(gpu, ora)
+
+
+BENCH = [("naive", vro.NAIVE, 1, 0), ("static_ballot_64", vro.STATIC_BALLOT, 64, 0),
+         ("dyn_sort_256_256", vro.DYN_SORT, 256, 256), ("dyn_hash_256_256", vro.DYN_HASH, 256, 256),
+         ("dyn_phash_256_256", vro.DYN_PHASH, 256, 256)]
+
+
+@pytest.mark.parametrize("sname,strategy,bt,nu", BENCH, ids=[s[0] for s in BENCH])
+def test_parity_bench_launch_configuration(stage, ico8, sname, strategy, bt, nu):
+    """The draws exactly as bench.py times them: corners and counters only,
+    dynamic draws with a plan built by vr_plan_dynamic (their units come from
+    the context's counters), twice in a row; corners bitwise."""
+    from paper_1805_08893_amd import vr
+    mesh, sp = ico8
+    _log(f"case bench configuration {sname}")
+    rc, ora = vro.process_draw(mesh.indices, mesh.vertices, sp, strategy, bt, {"max_unique": nu},
+                               tris=False, verts=False, local_idx=False, units=False)
+    assert rc == vro.OK
+    idx, vtx = _dev(mesh.indices), _dev(mesh.vertices)
+    plan = None
+    if strategy >= vro.DYN_SORT:
+        plan = torch.empty(mesh.num_tris + 2, dtype=torch.int32, device="cuda")
+        assert vr.vr_plan_dynamic(stage.ctx, idx, mesh.num_verts, nu, bt, plan) == vr.VR_OK
+    for rep in range(2):
+        res = stage.draw(idx, vtx, sp, strategy, bt, vr.make_opts(max_unique=nu, plan=plan), corners=True)
+        st, inv = stage.sync()
+        assert st == vr.VR_OK, vr.vr_last_error(stage.ctx)
+        assert inv == int(ora["counters"][0]) and int(res["counters"][0].item()) == inv
+        assert int(res["counters"][1].item()) == int(ora["counters"][1])
+        np.testing.assert_array_equal(res["corners"].cpu().numpy().view(np.uint32),
+                                      ora["corners"].view(np.uint32))
