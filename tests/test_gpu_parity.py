@@ -279,3 +279,27 @@ def test_parity_bench_launch_configuration(stage, ico8, sname, strategy, bt, nu)
         assert int(res["counters"][1].item()) == int(ora["counters"][1])
         np.testing.assert_array_equal(res["corners"].cpu().numpy().view(np.uint32),
                                       ora["corners"].view(np.uint32))
+
+
+def test_sort_wide_and_narrow_index_spans(stage):
+    """The sort's radix passes depend on each batch's index span (one pass
+    per 8 bits).  A stream of uniform random indices over 3M vertices (spans
+    of 22 bits: three passes), followed by a grid in Hilbert order (one or
+    two passes), has both kinds in one draw."""
+    V = 3_000_000
+    rng = np.random.default_rng(17)
+    wide = rng.integers(0, V, 3 * 6000, dtype=np.uint32)
+    grid = W.grid_mesh(60, 50, 5, "hilbert")
+    verts = np.zeros((V, 8), dtype=np.float32)
+    verts[:, :3] = rng.uniform(-1, 1, (V, 3)).astype(np.float32)
+    verts[:, 3:6] = np.float32(0.57735026)
+    verts[:grid.num_verts] = grid.vertices
+    mesh = W.Mesh("wide_then_narrow", np.concatenate([wide, grid.indices]), verts)
+    sp = W.shader_for_mesh(grid, W.SHADER_MVP, 5)
+    for sname, strategy, bt, nu in (("static_sort_64", vro.STATIC_SORT, 64, 0),
+                                    ("static_sort_256", vro.STATIC_SORT, 256, 0),
+                                    ("dyn_sort_341_256", vro.DYN_SORT, 341, 256)):
+        _log(f"case sort spans {sname}")
+        rc, ora = vro.process_draw(mesh.indices, mesh.vertices, sp, strategy, bt, {"max_unique": nu})
+        assert rc == vro.OK
+        compare(gpu_draw(stage, mesh, sp, strategy, bt, nu), ora)
