@@ -572,15 +572,15 @@ __host__ __device__ inline uint32_t ballot_lds_bytes(uint32_t batch_tris) {
 // s_keys; s_new is the wavefront's hand-over area.  When s_map is not NULL
 // it receives each corner's lane (local id).
 //
-// A group of 21 triangles is resolved by votes: each step takes four
-// pending lanes (lowest, highest, second lowest, second highest), broadcasts
-// their indices and ballots the lanes holding each of them and the lane that
-// already owns it.  Every lane learns the first lane of its value; values no
-// lane owns get the next free lanes in the order of their first lanes (a
-// popcount of the first lanes below), and the first lane hands the value to
-// the lane of its slot through LDS.  This is the sequential assignment of
-// Algorithm 1 (lowest unresolved lane first), with up to four distinct values
-// resolved per step.
+// A group of 21 triangles is resolved by votes, one per distinct value: the
+// lowest unresolved lane broadcasts its index, and ballots give the lanes
+// holding it (whose first occurrence is that lane) and the lane that already
+// owns it.  Values no lane owns then get the next free lanes in the order of
+// their first lanes (a popcount of the first-occurrence mask below), and the
+// first lane hands the value to the lane of its slot through LDS.  This is
+// the sequential assignment of Algorithm 1, with the slot bookkeeping taken
+// out of the per-value loop (the scalar unit, shared by a CU's wavefronts,
+// bounds this loop).
 __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t t0, uint32_t cur, uint32_t t1,
                                                  const uint32_t *s_keys, uint32_t pre, uint32_t *s_new,
                                                  uint8_t *s_map, RoundState &st) {
@@ -592,41 +592,32 @@ __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t t0,
         const bool act = lane < nc;
         const uint32_t pos = 3 * (cur - t0) + lane;
         const uint32_t k = act ? (pos < pre ? s_keys[pos] : fetch_index(A, 3ull * cur + lane)) : kEmpty;
-        uint64_t pend = ballot(act), fresh = 0;
+        // one vote per distinct value, lowest unresolved lane first: that
+        // lane is the value's first occurrence in the group
+        uint64_t pend = ballot(act);
         uint32_t first = lane, owner = kEmpty;
-        while (pend) {
-            const uint32_t ia = (uint32_t)__ffsll((long long)pend) - 1;
-            const uint32_t ib = 63u - (uint32_t)__clzll((long long)pend);
-            const uint64_t rest = pend & ~(1ull << ia) & ~(1ull << ib);
-            const uint32_t ic = rest ? (uint32_t)__ffsll((long long)rest) - 1 : ia;
-            const uint32_t id = rest ? 63u - (uint32_t)__clzll((long long)rest) : ib;
-            const uint32_t pick[4] = {ia, ib, ic, id};
-            if (fill == 0) {   // nothing owned yet in this round
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {   // values may coincide: the updates are idempotent
-                    const uint32_t cv = __builtin_amdgcn_readlane(k, pick[j]);
-                    const uint64_t same = ballot(k == cv);   // never empty: holds pick[j]
-                    const uint32_t fl = (uint32_t)__builtin_ctzll(same);
-                    first = __builtin_amdgcn_inverse_ballot_w64(same) ? fl : first;
-                    fresh |= 1ull << fl;
-                    pend &= ~same;
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t cv = __builtin_amdgcn_readlane(k, pick[j]);
-                    const uint64_t same = ballot(k == cv);   // never empty: holds pick[j]
-                    const uint64_t own = ballot(my_id == cv);
-                    const uint32_t fl = (uint32_t)__builtin_ctzll(same);
-                    const uint32_t ol = (uint32_t)__builtin_ctzll(own | (1ull << 63));   // used only if own
-                    const uint64_t held = own ? ~0ull : 0ull;
-                    owner = __builtin_amdgcn_inverse_ballot_w64(same & held) ? ol : owner;
-                    first = __builtin_amdgcn_inverse_ballot_w64(same & ~held) ? fl : first;
-                    fresh |= (1ull << fl) & ~held;
-                    pend &= ~same;
-                }
+        if (fill == 0) {   // nothing owned yet in this round
+            while (pend) {
+                const uint32_t pick = (uint32_t)__builtin_ctzll(pend);
+                const uint32_t cv = __builtin_amdgcn_readlane(k, pick);
+                const uint64_t same = ballot(k == cv);
+                first = __builtin_amdgcn_inverse_ballot_w64(same) ? pick : first;
+                pend &= ~same;
+            }
+        } else {
+            while (pend) {
+                const uint32_t pick = (uint32_t)__builtin_ctzll(pend);
+                const uint32_t cv = __builtin_amdgcn_readlane(k, pick);
+                const uint64_t same = ballot(k == cv);
+                const uint64_t own = ballot(my_id == cv);
+                const uint32_t ol = (uint32_t)__builtin_ctzll(own | (1ull << 63));   // used only if own
+                first = __builtin_amdgcn_inverse_ballot_w64(same) ? pick : first;
+                owner = __builtin_amdgcn_inverse_ballot_w64(own ? same : 0ull) ? ol : owner;
+                pend &= ~same;
             }
         }
+        // first occurrences of values no lane owns yet
+        const uint64_t fresh = ballot(act && owner == kEmpty && first == lane);
         const uint32_t slot = owner != kEmpty ? owner
                                               : fill + (uint32_t)__popcll(fresh & ((1ull << first) - 1ull));
         if (act && owner == kEmpty && first == lane && slot < (uint32_t)kWave) {
