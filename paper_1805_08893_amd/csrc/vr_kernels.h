@@ -609,12 +609,16 @@ __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t t0,
                 const uint32_t pick = (uint32_t)__builtin_ctzll(pend);
                 const uint32_t cv = __builtin_amdgcn_readlane(k, pick);
                 const uint64_t same = ballot(k == cv);
-                const uint64_t own = ballot(my_id == cv);
-                const uint32_t ol = (uint32_t)__builtin_ctzll(own | (1ull << 63));   // used only if own
-                first = __builtin_amdgcn_inverse_ballot_w64(same) ? pick : first;
-                owner = __builtin_amdgcn_inverse_ballot_w64(own ? same : 0ull) ? ol : owner;
+                // the owning lane, or lane 63 when none owns it (checked below)
+                const uint32_t ol = (uint32_t)__builtin_ctzll(ballot(my_id == cv) | (1ull << 63));
+                const bool in = __builtin_amdgcn_inverse_ballot_w64(same);
+                first = in ? pick : first;
+                owner = in ? ol : owner;
                 pend &= ~same;
             }
+            // a candidate owner counts only if it holds the lane's index
+            const uint32_t held = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(owner << 2), (int)my_id);
+            if (!act || held != k) owner = kEmpty;
         }
         // first occurrences of values no lane owns yet
         const uint64_t fresh = ballot(act && owner == kEmpty && first == lane);
