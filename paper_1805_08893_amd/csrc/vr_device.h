@@ -134,6 +134,28 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
+// Minimum / maximum over the 64 lanes with DPP (row shifts, then row
+// broadcasts; lanes without a source keep the identity), read from lane 63.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, kWave - 1);
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+    return __builtin_amdgcn_readlane(v, kWave - 1);
+}
+
 // Exclusive scan over one value per thread of an NT-thread workgroup.
 // `tmp` is LDS scratch of NT/64 words.  Contains barriers: call uniformly.
 template <int NT>
@@ -164,11 +186,8 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *tmp, u
 template <int NT>
 __device__ __forceinline__ void block_reduce_minmax(uint32_t &mn, uint32_t &mx, uint32_t *tmp) {
     constexpr int NW = NT / kWave;
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-        mn = min(mn, (uint32_t)__shfl_xor(mn, d, kWave));
-        mx = max(mx, (uint32_t)__shfl_xor(mx, d, kWave));
-    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
     __syncthreads();
     if (lane_id() == 0) {
         tmp[threadIdx.x / kWave] = mn;
@@ -189,8 +208,7 @@ __device__ __forceinline__ void block_reduce_minmax(uint32_t &mn, uint32_t &mx, 
 template <int NT>
 __device__ __forceinline__ uint32_t block_reduce_min(uint32_t v, uint32_t *tmp) {
     constexpr int NW = NT / kWave;
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v = min(v, (uint32_t)__shfl_xor(v, d, kWave));
+    v = wave_min(v);
     __syncthreads();
     if (lane_id() == 0) tmp[threadIdx.x / kWave] = v;
     __syncthreads();
@@ -204,8 +222,7 @@ __device__ __forceinline__ uint32_t block_reduce_min(uint32_t v, uint32_t *tmp) 
 template <int NT>
 __device__ __forceinline__ uint32_t block_reduce_max(uint32_t v, uint32_t *tmp) {
     constexpr int NW = NT / kWave;
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v = max(v, (uint32_t)__shfl_xor(v, d, kWave));
+    v = wave_max(v);
     __syncthreads();
     if (lane_id() == 0) tmp[threadIdx.x / kWave] = v;
     __syncthreads();
