@@ -533,12 +533,24 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
     }
 }
 
+// Unit base + workgroup index.
 template <int NT, int MODE, int KIND>
-__global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh) {
+__global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh, uint32_t base) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const uint32_t nb = launch_units(A, batch_count(A));
-    if (blockIdx.x >= nb) return;
-    dedup_unit<NT, MODE, KIND>(A, sh, blockIdx.x, nb, smem);
+    const uint32_t u = base + blockIdx.x;
+    if (u >= nb) return;
+    dedup_unit<NT, MODE, KIND>(A, sh, u, nb, smem);
+}
+
+// Every unit from base on, grid-stride: the part of a dynamic draw beyond
+// the fewest units it can have (without prefix outputs only: the look-back
+// needs each unit's predecessor running or done).
+template <int NT, int MODE, int KIND>
+__global__ __launch_bounds__(NT) void k_dedup_rest(DrawArgs A, vr_shader_params sh, uint32_t base) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const uint32_t nb = launch_units(A, batch_count(A));
+    for (uint32_t u = base + blockIdx.x; u < nb; u += gridDim.x) dedup_unit<NT, MODE, KIND>(A, sh, u, nb, smem);
 }
 
 // ---------------------------------------------------------------------------

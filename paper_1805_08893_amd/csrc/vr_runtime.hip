@@ -232,9 +232,26 @@ vr_status check_args(vr_ctx *c, uint64_t num_indices, const vr_shader_params *sh
     return VR_OK;
 }
 
+// A static draw's units are exactly known.  A dynamic draw has at least
+// ceil(T / N_pmax) units (exactly that many when every batch is full) and at
+// most the host-side bound: the first launch covers the fewest, a second
+// covers the rest, grid-stride over 8 workgroups per CU when the units may
+// come in any order (no prefix outputs), else one workgroup per unit.
 template <int NT, int MODE, int KIND>
 void launch_dedup(vr_ctx *c, const DrawArgs &A, const vr_shader_params &sh, uint32_t lds, uint64_t units) {
-    hipLaunchKernelGGL((k_dedup<NT, MODE, KIND>), dim3((uint32_t)units), dim3(NT), lds, c->stream, A, sh);
+    uint64_t first = units;
+    if (A.plan) first = std::min<uint64_t>(units, (A.T + A.batch_tris - 1) / A.batch_tris);
+    if (first)
+        hipLaunchKernelGGL((k_dedup<NT, MODE, KIND>), dim3((uint32_t)first), dim3(NT), lds, c->stream, A, sh, 0u);
+    if (units > first) {
+        if (A.need_prefix)
+            hipLaunchKernelGGL((k_dedup<NT, MODE, KIND>), dim3((uint32_t)(units - first)), dim3(NT), lds, c->stream, A,
+                               sh, (uint32_t)first);
+        else
+            hipLaunchKernelGGL((k_dedup_rest<NT, MODE, KIND>),
+                               dim3((uint32_t)std::min<uint64_t>(units - first, 8ull * c->num_cus)), dim3(NT), lds,
+                               c->stream, A, sh, (uint32_t)first);
+    }
 }
 
 template <int MODE, int KIND>
