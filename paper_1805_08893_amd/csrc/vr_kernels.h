@@ -232,7 +232,7 @@ __host__ __device__ inline DedupLds dedup_lds_layout(int mode, uint32_t max_idx,
     DedupLds L{};
     uint32_t off = 0;
     L.keys = off;  off += align16(4 * max_idx);
-    L.local = off; off += align16(4 * max_idx);
+    L.local = off; off += align16(2 * max_idx);   // uint16: hash slots < 4096, then ids < max_idx
     if (mode == kSort) {
         L.pairs = off; off += align16(4 * max_idx);   // two uint16 position buffers
         L.table = L.first = 0;
@@ -287,7 +287,7 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
                                            unsigned char *smem) {
     const DedupLds L = dedup_lds_layout(MODE, A.max_idx, A.max_uniq, A.hash_bits, NT);
     uint32_t *s_keys = (uint32_t *)(smem + L.keys);
-    uint32_t *s_local = (uint32_t *)(smem + L.local);
+    uint16_t *s_local = (uint16_t *)(smem + L.local);
     uint32_t *s_uniq = (uint32_t *)(smem + L.uniq);
     f4 *s_sv = (f4 *)(smem + L.sv);
     uint32_t *s_tmp = (uint32_t *)(smem + L.tmp);
@@ -410,7 +410,7 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
             uint32_t r = block_excl_scan<NT>(cnt, s_tmp, inv);
             for (uint32_t i = lo; i < hi; ++i) {
                 const uint32_t p = src[i], k = s_keys[p];
-                s_local[p] = r;
+                s_local[p] = (uint16_t)r;
                 if (i + 1 == n || k != s_keys[src[i + 1]]) s_uniq[r++] = k;
             }
         } else {
@@ -435,7 +435,7 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
                         }
                         p = (p + 1) & mask;
                     }
-                    s_local[i] = p;
+                    s_local[i] = (uint16_t)p;
                     atomicMin(&s_first[p], i);
                 }
             } else {
@@ -491,7 +491,7 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
                         pend &= pend - 1;
                     }
                     if (act) {
-                        s_local[i] = slot;
+                        s_local[i] = (uint16_t)slot;
                         atomicMin(&s_first[slot], i);
                     }
                 }
@@ -509,7 +509,7 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
             for (uint32_t i = tid; i < n; i += NT)
                 if (s_first[s_local[i]] == i) s_first[s_local[i]] = s_keys[i] | 0x80000000u;
             __syncthreads();
-            for (uint32_t i = tid; i < n; i += NT) s_local[i] = s_first[s_local[i]] & 0x7FFFFFFFu;
+            for (uint32_t i = tid; i < n; i += NT) s_local[i] = (uint16_t)(s_first[s_local[i]] & 0x7FFFFFFFu);
         }
 
         if (inv > A.max_uniq) {   // only with a plan built for a larger N_u
