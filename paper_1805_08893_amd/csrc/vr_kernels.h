@@ -417,17 +417,31 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
             uint32_t *s_table = (uint32_t *)(smem + L.table);
             uint32_t *s_first = (uint32_t *)(smem + L.first);
             const uint32_t S = 1u << A.hash_bits, mask = S - 1;
+            // Ids are visible only in the indexed outputs and local ids; then
+            // they are made canonical (first-occurrence order).  Otherwise a
+            // key's id comes from a counter taken by the lane that inserted
+            // it (Algorithm 3), and the corners are the same either way.
+            const bool canon = A.need_prefix || A.local_idx;
+            __shared__ uint32_t s_count;
             for (uint32_t s = tid; s < S; s += NT) {
                 s_table[s] = kEmpty;
                 s_first[s] = kEmpty;
             }
+            if (tid == 0) s_count = 0;
             __syncthreads();
+            // the inserting lane of a new key takes the next id
+            auto take_id = [&](uint32_t slot, uint32_t key) {
+                const uint32_t id = atomicAdd(&s_count, 1u);
+                s_first[slot] = id;
+                if (id < A.max_uniq) s_uniq[id] = key;
+            };
             if (MODE == kHash) {
                 for (uint32_t i = tid; i < n; i += NT) {
                     const uint32_t k = s_keys[i];
                     uint32_t p = hash_slot(k, A.hash_bits);
                     for (uint32_t probe = 0;; ++probe) {   // linear probing; S >= distinct keys
                         const uint32_t prev = atomicCAS(&s_table[p], kEmpty, k);
+                        if (prev == kEmpty && !canon) take_id(p, k);
                         if (prev == kEmpty || prev == k) break;
                         if (probe >= mask) {              // table full: only with foreign plans
                             raise_error(A.err, VR_ERR_CAPACITY);
@@ -436,7 +450,7 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
                         p = (p + 1) & mask;
                     }
                     s_local[i] = (uint16_t)p;
-                    atomicMin(&s_first[p], i);
+                    if (canon) atomicMin(&s_first[p], i);
                 }
             } else {
                 // wave-uniform sweep so the cooperative path sees every lane
@@ -449,6 +463,7 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
                     bool placed = !act;
                     for (uint32_t r = 0; r < A.probes && !placed; ++r) {
                         const uint32_t prev = atomicCAS(&s_table[p], kEmpty, k);
+                        if (prev == kEmpty && !canon) take_id(p, k);
                         if (prev == kEmpty || prev == k) {
                             slot = p;
                             placed = true;
@@ -477,7 +492,10 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
                             const uint32_t w = (uint32_t)__ffsll((long long)hit) - 1;
                             const uint32_t ws = (start + w) & mask;
                             uint32_t got = 0;
-                            if (lane == w) got = atomicCAS(&s_table[ws], kEmpty, key);
+                            if (lane == w) {
+                                got = atomicCAS(&s_table[ws], kEmpty, key);
+                                if (got == kEmpty && !canon) take_id(ws, key);
+                            }
                             got = __builtin_amdgcn_readlane(got, w);
                             if (got == kEmpty || got == key) {
                                 if (lane == Lr) {
@@ -492,24 +510,26 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
                     }
                     if (act) {
                         s_local[i] = (uint16_t)slot;
-                        atomicMin(&s_first[slot], i);
+                        if (canon) atomicMin(&s_first[slot], i);
                     }
                 }
             }
             __syncthreads();
-            // canonical ids: a slot's id is the rank of its first position
-            inv = rank_flagged<NT>(
-                n, s_tmp, [&](uint32_t i) { return s_first[s_local[i]] == i; },
-                [&](uint32_t i, uint32_t r) {
-                    s_uniq[r] = s_keys[i];
-                    s_keys[i] = r;   // stash the rank; the slot is rewritten below
-                });
-            __syncthreads();
-            // first positions now carry ranks
-            for (uint32_t i = tid; i < n; i += NT)
-                if (s_first[s_local[i]] == i) s_first[s_local[i]] = s_keys[i] | 0x80000000u;
-            __syncthreads();
-            for (uint32_t i = tid; i < n; i += NT) s_local[i] = (uint16_t)(s_first[s_local[i]] & 0x7FFFFFFFu);
+            if (canon) {
+                // canonical ids: a slot's id is the rank of its first position;
+                // every flag is read before the scan's barriers, so the first
+                // position can overwrite its slot's word with the rank
+                inv = rank_flagged<NT>(
+                    n, s_tmp, [&](uint32_t i) { return s_first[s_local[i]] == i; },
+                    [&](uint32_t i, uint32_t r) {
+                        s_uniq[r] = s_keys[i];
+                        s_first[s_local[i]] = r;
+                    });
+                __syncthreads();
+            } else {
+                inv = s_count;
+            }
+            for (uint32_t i = tid; i < n; i += NT) s_local[i] = (uint16_t)s_first[s_local[i]];
         }
 
         if (inv > A.max_uniq) {   // only with a plan built for a larger N_u
