@@ -215,14 +215,117 @@ def sweep(mesh, sp, reps=10):
     stage.close()
 
 
+def measure_draw(stage, idx, vtx, V, sp, strategy, bt, nu=0, reps=20, flush=None):
+    """One configuration: plan time (dynamic), main-kernel time from the
+    library's HIP events, draw time (events around the whole call) p50/p99,
+    invocations and the roofline fractions.  With `flush` (a device tensor)
+    the caches are overwritten before every timed draw (cold runs)."""
+    import torch
+    from paper_1805_08893_amd import vr
+    T = idx.numel() // 3
+    sh = vr.make_shader(sp)
+    plan = None
+    plan_ms = None
+    if strategy in vr.DYNAMIC:
+        plan = torch.empty(T + 2, dtype=torch.int32, device="cuda")
+        vr.vr_set_kernel_timing(stage.ctx, True)
+        vr.vr_kernel_times(stage.ctx)
+        for _ in range(max(3, reps // 4)):
+            stage.check(vr.vr_plan_dynamic(stage.ctx, idx, V, nu, bt, plan))
+        plan_ms = float(np.median(vr.vr_kernel_times(stage.ctx)))
+        vr.vr_set_kernel_timing(stage.ctx, False)
+    out = stage.alloc_outputs(T, strategy, bt, corners=True)
+    o = vr.make_opts(max_unique=nu, plan=plan)
+    for _ in range(3):
+        stage.check(vr.vr_process_draw(stage.ctx, idx, vtx, sh, strategy, bt, o, stage.describe(out)))
+    st, _ = stage.sync()
+    stage.check(st)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    vr.vr_set_kernel_timing(stage.ctx, True)
+    vr.vr_kernel_times(stage.ctx)
+    for e0, e1 in ev:
+        if flush is not None:
+            flush.fill_(1.0)
+        e0.record()
+        stage.check(vr.vr_process_draw(stage.ctx, idx, vtx, sh, strategy, bt, o, stage.describe(out)))
+        e1.record()
+    torch.cuda.synchronize()
+    kms = np.array(vr.vr_kernel_times(stage.ctx), dtype=np.float64)
+    vr.vr_set_kernel_timing(stage.ctx, False)
+    st, _ = stage.sync()
+    stage.check(st)
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    inv = int(out["counters"][0].item())
+    U = int(V)
+    k = float(np.median(kms))
+    alg = 12 * T + 32 * min(U, inv) + 144 * T
+    return {"batch_tris": bt, "max_unique": nu, "kernel_ms_p50": k, "draw_ms_p50": float(np.percentile(ms, 50)),
+            "draw_ms_p99": float(np.percentile(ms, 99)), "plan_ms_p50": plan_ms, "invocations": inv,
+            "reuse": 1.0 - inv / (3.0 * T), "tri_per_s": T / (k * 1e-3),
+            "hbm_frac": alg / (k * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "alu_frac": inv * shader_flops(sp) / (k * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS}
+
+
+def plain_latency(stage, reps=50):
+    """The small grid (64 x 64 vertices, 7,938 triangles, row-major, MVP):
+    launch-latency bound, so the latency of one draw is reported: GPU time
+    between events, and the host's time from the call to the completed draw."""
+    import torch
+    from paper_1805_08893_amd import vr
+    from paper_1805_08893_amd import workloads as W
+    mesh, sp = W.grid64_scan_mvp()
+    idx = torch.from_numpy(mesh.indices.view(np.int32)).cuda()
+    vtx = torch.from_numpy(mesh.vertices).cuda()
+    out = {}
+    for name, s, bt in (("naive", vr.VR_NAIVE, 1), ("static_sort_64", vr.VR_STATIC_SORT, 64)):
+        r = measure_draw(stage, idx, vtx, mesh.num_verts, sp, s, bt, reps=reps)
+        res = stage.alloc_outputs(mesh.num_tris, s, bt, corners=True)
+        sh = vr.make_shader(sp)
+        wall = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            stage.check(vr.vr_process_draw(stage.ctx, idx, vtx, sh, s, bt, None, stage.describe(res)))
+            torch.cuda.synchronize()
+            wall.append((time.perf_counter() - t0) * 1e3)
+        r.update({"host_ms_p50": float(np.percentile(wall, 50)), "host_ms_p99": float(np.percentile(wall, 99))})
+        out[name] = r
+    stage.check(stage.sync()[0])
+    return {"workload": "grid64_scan_mvp", "triangles": mesh.num_tris, "draws": out}
+
+
+def heavy_orders(stage, reps=10):
+    """The heavy shader on a large grid (2048 x 2048 vertices, 8,380,418
+    triangles, normal offset with 64 iterations) in Hilbert and in fully
+    random triangle order: naive, dynamic ballot (N_u 64 / N_pmax 85) and
+    dynamic hash (256 / 341)."""
+    import torch
+    from paper_1805_08893_amd import vr
+    from paper_1805_08893_amd import workloads as W
+    out = {}
+    for order in ("hilbert", "random"):
+        mesh, sp = W.grid2048_offset64(order)
+        idx = torch.from_numpy(mesh.indices.view(np.int32)).cuda()
+        vtx = torch.from_numpy(mesh.vertices).cuda()
+        out[order] = {name: measure_draw(stage, idx, vtx, mesh.num_verts, sp, s, bt, nu, reps=reps)
+                      for name, s, bt, nu in (("naive", vr.VR_NAIVE, 1, 0), ("dyn_ballot", vr.VR_DYN_BALLOT, 85, 64),
+                                              ("dyn_hash", vr.VR_DYN_HASH, 341, 256))}
+        del idx, vtx
+        torch.cuda.empty_cache()
+        progress(f"heavy {order} done")
+    return {"workload": "grid2048_offset64", "triangles": 2 * 2047 * 2047, "orders": out}
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def serving_benchmark(stage, seed=11, n=2000, rate=500.0, budget=64 << 30):
-    """A Poisson stream of draw requests against 200 resident meshes, served by
-    the continuous-batching server and by the same server launching every
-    request alone; plus a burst of the same requests for peak throughput."""
+def serving_benchmark(stage, seed=11, n=2000, rate=500.0, budget=64 << 30, small_budget=256 << 20):
+    """A Poisson stream of draw requests against 200 resident meshes (sizes
+    log-normal around 20k triangles, clamped to [1k, 2M]; a request draws a
+    whole mesh with Phong lighting of 1..16 lights), served by the
+    continuous-batching server and by the same server launching every
+    request alone; a burst of the same requests for peak throughput; and the
+    stream again under a 256 MB result budget (queueing and rejections)."""
     import torch
     from paper_1805_08893_amd import vr, serve
     from paper_1805_08893_amd import workloads as W
@@ -234,25 +337,36 @@ def serving_benchmark(stage, seed=11, n=2000, rate=500.0, budget=64 << 30):
     dev = [(torch.from_numpy(m.indices.view(np.int32)).cuda(), torch.from_numpy(m.vertices).cuda()) for m in bases]
     shaders = {}
     tuner = Autotuner(stage.ctx)
-    plan_of = []
+    cfg_of = {}
     for i in range(n):
-        b, start, _ = pool[tr["mesh"][i]]
-        L, size = int(tr["lights"][i]), int(tr["size"][i])
+        m, L = int(tr["mesh"][i]), int(tr["lights"][i])
+        b, start, size = pool[m]
         if (b, L) not in shaders:
             sp = W.shader_for_mesh(bases[b], W.SHADER_PHONG, seed + b, num_lights=L)
             shaders[(b, L)] = (sp, vr.make_shader(sp))
-        idx = dev[b][0][3 * start:3 * (start + size)]
-        host = bases[b].indices[3 * start:3 * (start + size)]
-        _, cfg = tuner.choose(idx, host, dev[b][1], shaders[(b, L)][0])
-        plan_of.append(cfg)
+        if (m, L) not in cfg_of:
+            idx = dev[b][0][3 * start:3 * (start + size)]
+            host = bases[b].indices[3 * start:3 * (start + size)]
+            cfg_of[(m, L)] = tuner.choose(idx, host, dev[b][1], shaders[(b, L)][0])[1]
     stage.check(stage.sync()[0])
+
+    def requests(ids):
+        out = []
+        for i in range(n):
+            m, L = int(tr["mesh"][i]), int(tr["lights"][i])
+            s, bt, nu = cfg_of[(m, L)]
+            out.append(vr.make_request(ids[m], pool[m][2], shaders[(pool[m][0], L)][1], s, bt, nu, user=i))
+        return out
+
+    def keep(srv):
+        return {k: v for k, v in srv.stats().items()
+                if k in ("ticks", "peak_reserved_bytes", "admission_blocked", "max_tick_draws", "max_pending",
+                         "plan_bytes", "rejected")}
 
     def run(max_tick_draws):
         with serve.Server(budget, max_inflight=2, max_tick_draws=max_tick_draws) as srv:
-            ids = [srv.add_mesh(dev[b][0][3 * start:], dev[b][1]) for b, start, _ in pool]
-            reqs = [vr.make_request(ids[tr["mesh"][i]], int(tr["size"][i]),
-                                    shaders[(pool[tr["mesh"][i]][0], int(tr["lights"][i]))][1],
-                                    plan_of[i][0], plan_of[i][1], plan_of[i][2], user=i) for i in range(n)]
+            ids = [srv.add_mesh(dev[b][0][3 * start:3 * (start + size)], dev[b][1]) for b, start, size in pool]
+            reqs = requests(ids)
             for r in reqs:                      # warm-up: builds and caches every plan
                 srv.submit(r)
             srv.drain(n)
@@ -267,8 +381,24 @@ def serving_benchmark(stage, seed=11, n=2000, rate=500.0, budget=64 << 30):
             out["burst_tri_per_s"] = burst["tri_per_s"]
             out["burst_wall_s"] = burst["wall_s"]
             out["burst_requests_per_tick"] = burst["requests_per_tick"]
-            out["stats"] = {k: v for k, v in srv.stats().items()
-                            if k in ("ticks", "peak_reserved_bytes", "admission_blocked", "max_tick_draws", "plan_bytes")}
+            out["stats"] = keep(srv)
+            return out
+
+    def run_small():
+        with serve.Server(small_budget, max_inflight=2) as srv:
+            ids = [srv.add_mesh(dev[b][0][3 * start:3 * (start + size)], dev[b][1]) for b, start, size in pool]
+            reqs = requests(ids)
+            rejected = []
+            got, _, wall = serve.replay(srv, reqs, tr["arrival"], rejected=rejected)
+            out = serve.summarize(got, wall)
+            out["rejected_requests"] = len(rejected)
+            # burst: admission waits for released results
+            rej = []
+            got, _, wall = serve.replay(srv, reqs, np.zeros(n), rejected=rej)
+            b = serve.summarize(got, wall)
+            out.update(burst_tri_per_s=b["tri_per_s"], burst_wall_s=b["wall_s"],
+                       burst_queue_ms_p99=b["queue_ms_p99"], burst_latency_ms_p99=b["latency_ms_p99"])
+            out["stats"] = keep(srv)
             return out
 
     progress("serving: configurations chosen")
@@ -276,8 +406,13 @@ def serving_benchmark(stage, seed=11, n=2000, rate=500.0, budget=64 << 30):
     progress("serving: batched server done")
     single = run(1)
     progress("serving: per-request launches done")
+    small = run_small()
+    progress("serving: 256 MB budget done")
+    sizes = np.array([p[2] for p in pool])
     return {"requests": n, "rate_req_per_s": rate, "mean_tris": float(tr["size"].mean()),
-            "meshes": len(pool), "budget_bytes": budget, "batched": batched, "per_request_launch": single}
+            "meshes": len(pool), "mesh_tris_p50": float(np.median(sizes)), "mesh_tris_max": int(sizes.max()),
+            "budget_bytes": budget, "batched": batched, "per_request_launch": single,
+            "budget_256MB": small}
 
 
 def main():
@@ -291,6 +426,8 @@ def main():
     ap.add_argument("--only", default=None, help="run only this strategy in each step (profiling)")
     ap.add_argument("--no-scene", action="store_true", help="skip the many-draw frame measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the cold-cache runs, the small-grid latency and the heavy-shader orders")
     ap.add_argument("--sweep", action="store_true",
                     help="time every strategy over batch sizes 32..1024 on the workload and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -409,6 +546,9 @@ def main():
                   "reuse": 1.0 - inv / (3.0 * T), "speedup_vs_naive": None})
     for name, *_ in strategies:
         per[name]["speedup_vs_naive"] = (per["naive"]["ms_mean"] / per[name]["ms_mean"]) if "naive" in per else None
+        kms = per[name]["kernel_ms_mean"]
+        per[name]["hbm_frac"] = (12 * T + 32 * U + 144 * T) / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS
+        per[name]["alu_frac"] = per[name]["invocations"] * shader_flops(sp) / (kms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS
 
     # dominant kernel: the main kernel of the slowest draw of the step, timed
     # with HIP events around its launch on the library's stream
@@ -444,6 +584,22 @@ def main():
                "sample": f"{args.cpu_passes} pass(es) of the full step (5 strategies x {T} triangles), "
                          f"single-threaded C oracle, {t_cpu:.1f} s"}
 
+    cold = None
+    if not args.only and not args.no_extra:
+        # the same draws with the caches overwritten (1 GiB) before each one
+        flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        cold = {name: measure_draw(stage, idx, vtx, V, sp, s, bt, o.get("max_unique", 0), reps=5, flush=flush)
+                for name, s, bt, o in strategies}
+        del flush
+        torch.cuda.empty_cache()
+        progress("cold runs done")
+    plain = heavy = None
+    if not args.only and not args.no_extra:
+        try:
+            plain = plain_latency(stage)
+            heavy = heavy_orders(stage)
+        except Exception as exc:   # the headline line must still be printed
+            heavy = {"error": repr(exc)}
     scene = None
     if not args.no_scene and not args.only:
         try:
@@ -465,7 +621,8 @@ def main():
                        "unique_vertices": U, "strategies": [s[0] for s in strategies],
                        "static_batch_tris": 64, "dynamic_max_unique": NU, "dynamic_max_tris": NP,
                        "output": "per-corner shaded vertices + invocation counters"},
-            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "scene": scene, "serving": serving}
+            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "cold": cold, "plain": plain, "heavy": heavy, "scene": scene,
+            "serving": serving}
     print(json.dumps(line), flush=True)
     stage.close()
 

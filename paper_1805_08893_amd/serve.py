@@ -80,20 +80,28 @@ class Server:
         return got
 
 
-def replay(server: Server, requests, arrivals, timeout_s=120.0):
+def replay(server: Server, requests, arrivals, timeout_s=120.0, rejected=None):
     """Submits requests[i] at arrivals[i] seconds after the start (a Poisson
     stream), releasing results as they finish.  Returns (completions,
-    submit lateness in seconds, wall seconds)."""
+    submit lateness in seconds, wall seconds).  With a list for `rejected`,
+    requests the budget can never hold are recorded there by index instead
+    of raising."""
     n = len(requests)
     got, late = [], np.zeros(n)
     t0 = time.perf_counter()
     i = 0
-    while len(got) < n:
+    expect = n
+    while len(got) < expect:
         now = time.perf_counter() - t0
         if now > timeout_s:
-            raise TimeoutError(f"{len(got)} of {n} requests finished")
+            raise TimeoutError(f"{len(got)} of {expect} requests finished")
         while i < n and arrivals[i] <= now:
-            server.submit(requests[i])
+            st, _ = vr.vr_server_submit(server.h, requests[i])
+            if st == vr.VR_ERR_CAPACITY and rejected is not None:
+                rejected.append(i)
+                expect -= 1
+            else:
+                server.check(st)
             late[i] = now - arrivals[i]
             i += 1
             now = time.perf_counter() - t0

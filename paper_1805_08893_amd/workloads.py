@@ -437,40 +437,31 @@ def serving_bases(seed: int = 11, grid_n: int = 1024, ico_level: int = 8):
             icosphere_mesh(ico_level, seed + 2, "hilbert"), icosphere_mesh(ico_level, seed + 3, "scan")]
 
 
-def serving_pool(bases, seed: int = 12, n: int = 200, min_tris: int = 1000):
-    """n meshes, each a contiguous window (base, first triangle, triangles)
-    of a base index buffer; the first two windows of every base start at 0
-    and span the whole base, the rest start at a seeded triangle in the first
-    half and run to the end."""
+def serving_pool(bases, seed: int = 12, n: int = 200, size_median: int = 20000, sigma: float = 1.5,
+                 size_lo: int = 1000, size_hi: int = 2_000_000):
+    """n meshes with sizes log-normal (median `size_median`, `sigma`) clamped
+    to [size_lo, size_hi] and to the base: mesh m is a contiguous window
+    (base m mod len(bases), first triangle, triangles) of a base index
+    buffer, starting at a seeded triangle."""
     rng = np.random.default_rng(seed)
+    sizes = np.clip(np.exp(rng.normal(np.log(size_median), sigma, n)), size_lo, size_hi).astype(np.int64)
     pool = []
     for m in range(n):
         b = m % len(bases)
         T = bases[b].num_tris
-        start = 0 if m < 2 * len(bases) else int(rng.integers(0, max(1, min(T // 2, T - min_tris))))
-        pool.append((b, start, T - start))
+        size = int(min(sizes[m], T))
+        start = int(rng.integers(0, T - size + 1))
+        pool.append((b, start, size))
     return pool
 
 
-def serving_trace(pool, seed: int = 13, n: int = 2000, rate: float = 500.0, size_lo: int = 1000,
-                  size_hi: int = 2_000_000, lights=(1, 16)):
-    """Poisson arrivals at `rate` per second; sizes log-normal with median
-    sqrt(size_lo * size_hi) and sigma ln(size_hi / size_lo) / 4, clipped to
-    [size_lo, size_hi]; each request takes the first `size` triangles of a
-    pool mesh drawn uniformly among those long enough (the longest when none
-    is); Phong lighting with a uniform number of lights."""
+def serving_trace(pool, seed: int = 13, n: int = 2000, rate: float = 500.0, lights=(1, 16)):
+    """Poisson arrivals at `rate` per second; a request draws a whole pool
+    mesh, uniformly, with Phong lighting of a uniform number of lights."""
     rng = np.random.default_rng(seed)
     arrival = np.cumsum(rng.exponential(1.0 / rate, n))
     arrival -= arrival[0]
-    mu, sigma = 0.5 * np.log(size_lo * size_hi), np.log(size_hi / size_lo) / 4
-    size = np.clip(np.exp(rng.normal(mu, sigma, n)), size_lo, size_hi).astype(np.int64)
-    lens = np.array([p[2] for p in pool])
-    mesh = np.empty(n, dtype=np.int64)
-    for i in range(n):
-        ok = np.nonzero(lens >= size[i])[0]
-        if ok.size == 0:
-            ok = np.nonzero(lens == lens.max())[0]
-            size[i] = lens.max()
-        mesh[i] = ok[rng.integers(0, ok.size)]
+    mesh = rng.integers(0, len(pool), n)
+    size = np.array([pool[m][2] for m in mesh], dtype=np.int64)
     nl = rng.integers(lights[0], lights[1] + 1, n)
     return {"arrival": arrival, "size": size, "mesh": mesh, "lights": nl}
