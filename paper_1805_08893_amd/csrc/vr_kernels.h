@@ -93,9 +93,24 @@ __device__ __forceinline__ void write_unit(const DrawArgs &A, uint32_t t0, uint3
                                            uint32_t tid) {
     const uint32_t ncorner = 3 * ntri;
     if (A.corners) {
+        // four rows per lane at a time, so that their LDS reads overlap
         f4 *dst = A.corners + 9ull * t0;
         const uint32_t cnt = 9 * ntri;
-        for (uint32_t q = tid; q < cnt; q += NT) {
+        uint32_t q = tid;
+        for (; q + 3 * NT < cnt; q += 4 * NT) {
+            uint32_t at[4];
+            f4 row[4];
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) {
+                const uint32_t x = q + i * NT, k = x / 3;
+                at[i] = 3 * (uint32_t)s_local[k] + (x - 3 * k);
+            }
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) row[i] = s_sv[at[i]];
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) __builtin_nontemporal_store(row[i], dst + q + i * NT);
+        }
+        for (; q < cnt; q += NT) {
             const uint32_t k = q / 3, part = q - 3 * k;
             __builtin_nontemporal_store(s_sv[3 * (uint32_t)s_local[k] + part], dst + q);
         }
@@ -271,6 +286,85 @@ __device__ __forceinline__ uint32_t rank_flagged(uint32_t n, uint32_t *s_tmp, Fl
     return total;
 }
 
+// LSD radix sort of a unit's positions by index (Algorithm 2's sort): 8-bit
+// digits of (index - unit minimum), `passes` of them.  Within a pass, element
+// x of the current order is handled in round x / NT by thread x % NT; its
+// stable destination is the offset of (digit, round, wavefront) plus its
+// rank among the wavefront's lanes with the same digit, found with 8
+// ballots.  Counts (uint8) and offsets (uint16) are stored per digit
+// contiguously in `tab`, so the thread owning a digit scans them with word
+// accesses and clears the counts for the next pass.  RR is the round count
+// when known at compile time (R == RR), else 8 (R <= 8).  Returns the sorted
+// order (one of the two position buffers).
+template <int NT, uint32_t RR>
+__device__ __forceinline__ const uint16_t *radix_passes(const uint32_t *s_keys, uint16_t *src, uint16_t *dst,
+                                                        uint32_t n, uint32_t R, uint32_t kmin, uint32_t passes,
+                                                        uint32_t Gp, unsigned char *tab, uint32_t *s_tmp) {
+    constexpr uint32_t NW = NT / kWave;
+    constexpr uint32_t DP = NT >= 256 ? 1u : 256u / NT;   // digits per thread in the scan
+    const uint32_t tid = threadIdx.x, w = tid / kWave;
+    uint32_t *s_c32 = (uint32_t *)tab;              // [256][Gp] uint8 counts
+    uint2 *s_o64 = (uint2 *)(tab + 256 * Gp);       // [256][Gp] uint16 offsets
+    const uint16_t *s_o16 = (const uint16_t *)s_o64;
+    uint8_t *s_c8 = (uint8_t *)s_c32;
+    for (uint32_t pass = 0; pass < passes; ++pass) {
+        uint32_t dig[RR], rank[RR], pos[RR];
+#pragma unroll
+        for (uint32_t r = 0; r < RR; ++r) {
+            if (RR == 8 && r >= R) break;
+            const uint32_t x = r * NT + tid;
+            const bool act = x < n;
+            const uint32_t p = act ? src[x] : 0u;
+            const uint32_t d = act ? ((s_keys[p] - kmin) >> (8 * pass)) & 0xFFu : 0u;
+            uint64_t peers = ballot(act);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const uint64_t m = ballot((d >> bit) & 1u);
+                peers &= ((d >> bit) & 1u) ? m : ~m;
+            }
+            const uint32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+            if (act && rk == 0) s_c8[d * Gp + r * NW + w] = (uint8_t)__popcll(peers);
+            dig[r] = d;
+            rank[r] = rk;
+            pos[r] = p;
+        }
+        __syncthreads();
+        {   // exclusive offsets in (digit, round, wavefront) order
+            const uint32_t d0 = tid * DP, words = Gp / 4;
+            uint32_t sum = 0;
+            if (d0 < 256)
+                for (uint32_t j = 0; j < DP * words; ++j) {
+                    const uint32_t c = s_c32[d0 * words + j];
+                    sum += (c & 0xFFu) + ((c >> 8) & 0xFFu) + ((c >> 16) & 0xFFu) + (c >> 24);
+                }
+            uint32_t total;
+            uint32_t run = block_excl_scan<NT>(sum, s_tmp, total);
+            if (d0 < 256)
+                for (uint32_t j = 0; j < DP * words; ++j) {
+                    const uint32_t c = s_c32[d0 * words + j];
+                    s_c32[d0 * words + j] = 0;   // counts start at zero next pass
+                    const uint32_t o0 = run, o1 = o0 + (c & 0xFFu), o2 = o1 + ((c >> 8) & 0xFFu),
+                                   o3 = o2 + ((c >> 16) & 0xFFu);
+                    run = o3 + (c >> 24);
+                    s_o64[d0 * words + j] = make_uint2(o0 | (o1 << 16), o2 | (o3 << 16));
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t r = 0; r < RR; ++r) {
+            if (RR == 8 && r >= R) break;
+            const uint32_t x = r * NT + tid;
+            if (x < n) dst[s_o16[dig[r] * Gp + r * NW + w] + rank[r]] = (uint16_t)pos[r];
+        }
+        __syncthreads();
+        uint16_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    return src;
+}
+
 // ---------------------------------------------------------------------------
 // Batched deduplication + shading + assembly (Algorithms 2 and 3, and the
 // parallel-hashing variant).  Workgroup u owns unit u (no atomics to pick
@@ -308,26 +402,13 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
 
         uint32_t inv;
         if (MODE == kSort) {
-            // LSD radix sort of the positions by index (Algorithm 2's sort):
-            // 8-bit digits of (index - batch minimum), only as many passes as
-            // the batch's index range needs.  Within a pass, element x of the
-            // current order is handled in round x / NT by thread x % NT; its
-            // stable destination is the offset of (digit, round, wavefront)
-            // plus its rank among the wavefront's lanes with the same digit,
-            // found with 8 ballots.  Counts (uint8) and offsets (uint16) are
-            // stored per digit contiguously, so the thread owning a digit
-            // scans them with word accesses and clears the counts for the
-            // next pass.
+            // LSD radix sort of the positions by index (radix_passes), only
+            // as many passes as the unit's index range needs
             uint16_t *s_pos0 = (uint16_t *)(smem + L.pairs);
             uint16_t *s_pos1 = s_pos0 + A.max_idx;
-            constexpr uint32_t NW = NT / kWave;
-            constexpr uint32_t DP = NT >= 256 ? 1u : 256u / NT;   // digits per thread in the scan
             const uint32_t R = (n + NT - 1) / NT;   // <= 8: the launcher sizes NT >= max_idx / 8
             const uint32_t Gp = sort_groups(A.max_idx, NT);
             uint32_t *s_c32 = (uint32_t *)(smem + L.sv);                       // [256][Gp] uint8 counts
-            uint2 *s_o64 = (uint2 *)(smem + L.sv + 256 * Gp);                  // [256][Gp] uint16 offsets
-            const uint16_t *s_o16 = (const uint16_t *)s_o64;
-            uint8_t *s_c8 = (uint8_t *)s_c32;
             __syncthreads();
             uint32_t kmin = kEmpty, kmax = 0;
             for (uint32_t i = tid; i < n; i += NT) {
@@ -340,65 +421,12 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
             block_reduce_minmax<NT>(kmin, kmax, s_tmp);
             const uint32_t span = n ? kmax - kmin : 0u;
             const uint32_t passes = span ? (32u - __builtin_clz(span) + 7u) / 8u : 0u;
-            const uint32_t w = tid / kWave;
-            uint16_t *src = s_pos0, *dst = s_pos1;
-            for (uint32_t pass = 0; pass < passes; ++pass) {
-                uint32_t dig[8], rank[8], pos[8];
-#pragma unroll
-                for (uint32_t r = 0; r < 8; ++r) {
-                    if (r < R) {
-                        const uint32_t x = r * NT + tid;
-                        const bool act = x < n;
-                        const uint32_t p = act ? src[x] : 0u;
-                        const uint32_t d = act ? ((s_keys[p] - kmin) >> (8 * pass)) & 0xFFu : 0u;
-                        uint64_t peers = ballot(act);
-#pragma unroll
-                        for (int bit = 0; bit < 8; ++bit) {
-                            const uint64_t m = ballot((d >> bit) & 1u);
-                            peers &= ((d >> bit) & 1u) ? m : ~m;
-                        }
-                        const uint32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
-                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
-                        if (act && rk == 0) s_c8[d * Gp + r * NW + w] = (uint8_t)__popcll(peers);
-                        dig[r] = d;
-                        rank[r] = rk;
-                        pos[r] = p;
-                    }
-                }
-                __syncthreads();
-                {   // exclusive offsets in (digit, round, wavefront) order
-                    const uint32_t d0 = tid * DP, words = Gp / 4;
-                    uint32_t sum = 0;
-                    if (d0 < 256)
-                        for (uint32_t j = 0; j < DP * words; ++j) {
-                            const uint32_t c = s_c32[d0 * words + j];
-                            sum += (c & 0xFFu) + ((c >> 8) & 0xFFu) + ((c >> 16) & 0xFFu) + (c >> 24);
-                        }
-                    uint32_t total;
-                    uint32_t run = block_excl_scan<NT>(sum, s_tmp, total);
-                    if (d0 < 256)
-                        for (uint32_t j = 0; j < DP * words; ++j) {
-                            const uint32_t c = s_c32[d0 * words + j];
-                            s_c32[d0 * words + j] = 0;   // counts start at zero next pass
-                            const uint32_t o0 = run, o1 = o0 + (c & 0xFFu), o2 = o1 + ((c >> 8) & 0xFFu),
-                                           o3 = o2 + ((c >> 16) & 0xFFu);
-                            run = o3 + (c >> 24);
-                            s_o64[d0 * words + j] = make_uint2(o0 | (o1 << 16), o2 | (o3 << 16));
-                        }
-                }
-                __syncthreads();
-#pragma unroll
-                for (uint32_t r = 0; r < 8; ++r) {
-                    if (r < R) {
-                        const uint32_t x = r * NT + tid;
-                        if (x < n) dst[s_o16[dig[r] * Gp + r * NW + w] + rank[r]] = (uint16_t)pos[r];
-                    }
-                }
-                __syncthreads();
-                uint16_t *t = src;
-                src = dst;
-                dst = t;
-            }
+            // the round count fixed at compile time where it is small
+            const uint16_t *src;
+            if (R <= 1) src = radix_passes<NT, 1>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.sv, s_tmp);
+            else if (R == 2) src = radix_passes<NT, 2>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.sv, s_tmp);
+            else if (R == 3) src = radix_passes<NT, 3>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.sv, s_tmp);
+            else src = radix_passes<NT, 8>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.sv, s_tmp);
             // run ends of the sorted indices; the exclusive prefix over run
             // ends is the rank of every entry's run (Algorithm 2's marks and
             // prefix sum)
