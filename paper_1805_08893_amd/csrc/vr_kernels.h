@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_naive(DrawArgs A, vr_shader_params sh) 
 // LDS layout of the dedup kernel (bytes), shared with the host launcher.
 // ---------------------------------------------------------------------------
 struct DedupLds {
-    uint32_t keys, local, pairs, table, first, uniq, sv, tmp, total;
+    uint32_t keys, local, pairs, stab, table, first, uniq, sv, tmp, total;
 };
 
 __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
@@ -242,25 +242,30 @@ __host__ __device__ inline uint32_t sort_groups(uint32_t max_idx, uint32_t nt) {
     return (g + 3u) & ~3u;
 }
 
+// The local ids and the unique list live through the whole unit; the
+// shaded vertices (written after deduplication) share their region with
+// what deduplication alone uses: the indices, then the sort's two position
+// buffers and its per-digit counts (uint8) and offsets (uint16), or the
+// hash table and the first-position words.
 __host__ __device__ inline DedupLds dedup_lds_layout(int mode, uint32_t max_idx, uint32_t max_uniq,
                                                      uint32_t hash_bits, uint32_t nt) {
     DedupLds L{};
     uint32_t off = 0;
-    L.keys = off;  off += align16(4 * max_idx);
     L.local = off; off += align16(2 * max_idx);   // uint16: hash slots < 4096, then ids < max_idx
+    L.uniq = off;  off += align16(4 * max_uniq);
+    L.sv = off;
+    uint32_t d = off;
+    L.keys = d;    d += align16(4 * max_idx);
     if (mode == kSort) {
-        L.pairs = off; off += align16(4 * max_idx);   // two uint16 position buffers
+        L.pairs = d; d += align16(4 * max_idx);   // two uint16 position buffers
+        L.stab = d;  d += 3u * 256u * sort_groups(max_idx, nt);
         L.table = L.first = 0;
     } else {
-        L.pairs = 0;
-        L.table = off; off += align16(4u << hash_bits);
-        L.first = off; off += align16(4u << hash_bits);
+        L.pairs = L.stab = 0;
+        L.table = d; d += align16(4u << hash_bits);
+        L.first = d; d += align16(4u << hash_bits);
     }
-    L.uniq = off; off += align16(4 * max_uniq);
-    L.sv = off;
-    // the sort's per-digit counts (uint8) and offsets (uint16), 256 digits x
-    // sort_groups entries each, live in the shaded-vertex area before shading
-    off += mode == kSort ? max(48 * max_uniq, 3u * 256u * sort_groups(max_idx, nt)) : 48 * max_uniq;
+    off = max(align16(off + 48 * max_uniq), align16(d));
     L.tmp = off;  off += 64;
     L.total = off;
     return L;
@@ -408,7 +413,7 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
             uint16_t *s_pos1 = s_pos0 + A.max_idx;
             const uint32_t R = (n + NT - 1) / NT;   // <= 8: the launcher sizes NT >= max_idx / 8
             const uint32_t Gp = sort_groups(A.max_idx, NT);
-            uint32_t *s_c32 = (uint32_t *)(smem + L.sv);                       // [256][Gp] uint8 counts
+            uint32_t *s_c32 = (uint32_t *)(smem + L.stab);                     // [256][Gp] uint8 counts
             __syncthreads();
             uint32_t kmin = kEmpty, kmax = 0;
             for (uint32_t i = tid; i < n; i += NT) {
@@ -423,10 +428,10 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
             const uint32_t passes = span ? (32u - __builtin_clz(span) + 7u) / 8u : 0u;
             // the round count fixed at compile time where it is small
             const uint16_t *src;
-            if (R <= 1) src = radix_passes<NT, 1>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.sv, s_tmp);
-            else if (R == 2) src = radix_passes<NT, 2>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.sv, s_tmp);
-            else if (R == 3) src = radix_passes<NT, 3>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.sv, s_tmp);
-            else src = radix_passes<NT, 8>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.sv, s_tmp);
+            if (R <= 1) src = radix_passes<NT, 1>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.stab, s_tmp);
+            else if (R == 2) src = radix_passes<NT, 2>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.stab, s_tmp);
+            else if (R == 3) src = radix_passes<NT, 3>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.stab, s_tmp);
+            else src = radix_passes<NT, 8>(s_keys, s_pos0, s_pos1, n, R, kmin, passes, Gp, smem + L.stab, s_tmp);
             // run ends of the sorted indices; the exclusive prefix over run
             // ends is the rank of every entry's run (Algorithm 2's marks and
             // prefix sum)
