@@ -133,18 +133,18 @@ __device__ __forceinline__ void write_unit(const DrawArgs &A, uint32_t t0, uint3
 }
 
 // ---------------------------------------------------------------------------
-// End of a batched draw: one workgroup sums the per-batch aggregates into the
-// counters (no same-address atomics on the hot path) and clears the
-// look-back words for the next launch.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_finish(const uint32_t *plan, uint32_t num_batches, uint32_t status_cap,
-                                                 const unsigned long long *agg, unsigned long long *status,
-                                                 unsigned long long *counters, unsigned long long *total_inv) {
-    __shared__ unsigned long long part[16];
+// End of a batched draw: each workgroup sums a slice of the per-batch
+// aggregates and adds it to the counters (zeroed by the draw's first
+// kernel) and to the context total, one atomic per counter and workgroup,
+// and clears its slice of the look-back words for the next launch.
+__global__ __launch_bounds__(256) void k_finish(const uint32_t *plan, uint32_t num_batches, uint32_t status_cap,
+                                                const unsigned long long *agg, unsigned long long *status,
+                                                unsigned long long *counters, unsigned long long *total_inv) {
+    __shared__ unsigned long long part[4];
     uint32_t nb = plan ? plan[0] : num_batches;
     if (nb > status_cap) nb = status_cap;
     unsigned long long sum = 0;
-    for (uint32_t i = threadIdx.x; i < nb; i += 1024) {
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nb; i += gridDim.x * 256) {
         sum += agg[i];
         if (status) status[i] = 0;
     }
@@ -152,17 +152,19 @@ __global__ __launch_bounds__(1024) void k_finish(const uint32_t *plan, uint32_t 
     if (lane_id() == 0) part[threadIdx.x / kWave] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < 16; ++w) t += part[w];
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
         const unsigned long long inv = t & 0xFFFFFFFFull, units = t >> 32;
         if (counters) {
-            counters[0] = inv;
-            counters[1] = units;
-            counters[2] = 0;
-            counters[3] = 0;
+            atomicAdd(&counters[0], inv);
+            atomicAdd(&counters[1], units);
         }
-        *total_inv += inv;
+        atomicAdd(total_inv, inv);
     }
+}
+
+// The draw's first kernel clears its counters before k_finish adds to them.
+__device__ __forceinline__ void clear_counters(const DrawArgs &A) {
+    if (blockIdx.x == 0 && threadIdx.x < 4 && A.counters) A.counters[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -590,6 +592,7 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
 template <int NT, int MODE, int KIND>
 __global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh, uint32_t base) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    if (base == 0) clear_counters(A);
     const uint32_t nb = launch_units(A, batch_count(A));
     const uint32_t u = base + blockIdx.x;
     if (u >= nb) return;
@@ -782,6 +785,7 @@ constexpr uint32_t kBallotWaves = 4;
 template <int KIND>
 __global__ __launch_bounds__(kBallotWaves * 64) void k_ballot(DrawArgs A, vr_shader_params sh, uint32_t stride) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    clear_counters(A);
     const uint32_t nb = launch_units(A, batch_count(A));
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t b = blockIdx.x * kBallotWaves + w;

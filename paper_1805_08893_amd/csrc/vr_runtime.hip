@@ -681,7 +681,8 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
         else dispatch_kind<kPHash>(c, sh.kind, r.nt, A, sh, lds, nb_bound);
     }
     timed.done();
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, c->stream, A.plan, A.num_batches, A.status_cap,
+    const uint32_t fin = (uint32_t)std::min<uint64_t>(64, std::max<uint64_t>(1, (nb_bound + 2047) / 2048));
+    hipLaunchKernelGGL(k_finish, dim3(fin), dim3(256), 0, c->stream, A.plan, A.num_batches, A.status_cap,
                        (const unsigned long long *)A.agg, A.status, A.counters, A.total_inv);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
