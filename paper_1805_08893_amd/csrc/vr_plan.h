@@ -81,12 +81,22 @@ constexpr uint32_t kCheckBits = 11;                             // 2048 slots >=
 constexpr uint32_t kCheckPer = 3 * VR_MAX_BATCH_DYNAMIC / 256;  // corners per thread
 static_assert((1u << kCheckBits) >= 3 * VR_MAX_BATCH_DYNAMIC, "check table must hold every corner");
 
-__global__ __launch_bounds__(256) void k_plan_check(PlanArgs P) {
+__global__ __launch_bounds__(256) void k_plan_check(PlanArgs P, uint32_t *plan) {
     __shared__ uint32_t s_tab[1u << kCheckBits];
     __shared__ uint32_t s_tmp[4];
     const uint32_t tid = threadIdx.x;
     const uint32_t t0 = blockIdx.x * P.tmax, t1 = min(P.T, t0 + P.tmax);
     const uint32_t n = 3 * (t1 - t0);
+    // the aligned chain [K, 0, N_pmax, .., (K-1) N_pmax, T], written before
+    // it is verified: when a window fails, the general planner's kernels
+    // overwrite the count, the starts and the end
+    if (tid == 0) {
+        plan[1 + blockIdx.x] = t0;
+        if (blockIdx.x == 0) {
+            plan[0] = gridDim.x;
+            plan[1 + gridDim.x] = P.T;
+        }
+    }
     uint32_t key[kCheckPer];
 #pragma unroll
     for (uint32_t k = 0; k < kCheckPer; ++k) {
@@ -123,15 +133,6 @@ __global__ __launch_bounds__(256) void k_plan_check(PlanArgs P) {
     uint32_t distinct;
     block_excl_scan<256>(fresh, s_tmp, distinct);
     if (tid == 0 && distinct > P.cap) *P.fail = P.epoch;
-}
-
-// Writes the aligned chain [K, 0, N_pmax, .., (K-1) N_pmax, T] when it was
-// verified.
-__global__ __launch_bounds__(256) void k_plan_aligned(PlanArgs P, uint32_t *plan) {
-    if (!plan_is_aligned(P.fail, P.epoch)) return;
-    const uint32_t K = (P.T + P.tmax - 1) / P.tmax;
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < K + 2; i += gridDim.x * 256)
-        plan[i] = i == 0 ? K : (i == K + 1 ? P.T : (i - 1) * P.tmax);
 }
 
 // ---------------------------------------------------------------------------

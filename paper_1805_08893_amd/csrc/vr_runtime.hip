@@ -342,7 +342,7 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     P.epoch = c->plan_epoch;
     TimedRegion timed(c);
     const uint32_t K = (T + tmax - 1) / tmax;
-    hipLaunchKernelGGL(k_plan_check, dim3(K), dim3(256), 0, c->stream, P);
+    hipLaunchKernelGGL(k_plan_check, dim3(K), dim3(256), 0, c->stream, P, d_plan);
     if (tmax <= 256)
         hipLaunchKernelGGL(k_plan_next<256>, dim3((T + kNextBlock - 1) / kNextBlock), dim3(256), 0, c->stream, P);
     else
@@ -366,8 +366,6 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
                            (const uint32_t *)ncuts, d_plan);
     else
         hipLaunchKernelGGL(k_plan_pack, dim3(1), dim3(1024), 0, c->stream, P, (const uint32_t *)cuts, ncuts, d_plan);
-    hipLaunchKernelGGL(k_plan_aligned, dim3(std::min<uint32_t>(1024, (K + 2 + 255) / 256)), dim3(256), 0, c->stream, P,
-                       d_plan);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
 }
