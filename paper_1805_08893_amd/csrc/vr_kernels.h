@@ -73,6 +73,16 @@ __device__ __forceinline__ uint32_t fetch_index(const DrawArgs &A, uint64_t pos)
     return k;
 }
 
+// Shades the vertex whose 32 input bytes are (a, b) into dst[0..2].
+template <int KIND>
+__device__ __forceinline__ void shade_raw_to_lds(const vr_shader_params &sh, f4 a, f4 b, f4 *dst) {
+    float4 o0, o1, o2;
+    shade_vertex<KIND>(sh, make_float4(a.x, a.y, a.z, a.w), make_float4(b.x, b.y, b.z, b.w), o0, o1, o2);
+    dst[0] = f4{o0.x, o0.y, o0.z, o0.w};
+    dst[1] = f4{o1.x, o1.y, o1.z, o1.w};
+    dst[2] = f4{o2.x, o2.y, o2.z, o2.w};
+}
+
 template <int KIND>
 __device__ __forceinline__ void shade_to_lds(const DrawArgs &A, const vr_shader_params &sh, uint32_t v,
                                              f4 *dst) {
@@ -622,6 +632,7 @@ __global__ __launch_bounds__(NT) void k_dedup_rest(DrawArgs A, vr_shader_params 
 struct RoundState {
     uint32_t my_id;   // the vertex this lane shades in the round
     uint32_t fill;    // lanes in use (= invocations of the round)
+    f4 va, vb;        // its input, loaded when the lane took it (output sweep only)
 };
 
 // Indices of a batch a wavefront keeps in LDS (the rest, for batches of more
@@ -654,6 +665,7 @@ __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t t0,
                                                  uint8_t *s_map, RoundState &st) {
     const uint32_t lane = lane_id();
     uint32_t my_id = kEmpty, my_intro = kEmpty, fill = 0, done = 0;
+    f4 va = {}, vb = {};
     for (;;) {
         const uint32_t gt = min(21u, t1 - cur);
         const uint32_t nc = 3 * gt;
@@ -701,6 +713,10 @@ __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t t0,
         if (lane >= fill && lane < f) {
             my_id = s_new[lane];
             my_intro = s_new[kWave + lane];
+            if (s_map) {   // the output sweep: the load overlaps the rest of the round
+                va = A.vtx[2ull * my_id];
+                vb = A.vtx[2ull * my_id + 1];
+            }
         }
         const uint64_t bad = ballot(act && slot >= (uint32_t)kWave);
         const uint32_t acc = bad ? ((uint32_t)__ffsll((long long)bad) - 1) / 3 : gt;
@@ -718,6 +734,8 @@ __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t t0,
     }
     st.my_id = my_id;
     st.fill = fill;
+    st.va = va;
+    st.vb = vb;
     return cur;
 }
 
@@ -765,7 +783,7 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
     uint32_t r = 0, inv = 0;
     for (uint32_t cur = t0; cur < t1; ++r) {
         const uint32_t end = ballot_round(A, t0, cur, t1, s_keys, pre, s_new, s_map, st);
-        if (lane < st.fill) shade_to_lds<KIND>(A, sh, st.my_id, s_sv + 3 * lane);
+        if (lane < st.fill) shade_raw_to_lds<KIND>(sh, st.va, st.vb, s_sv + 3 * lane);
         wave_sync_lds();
         write_unit<64>(A, cur, end - cur, s_map, s_sv, st.fill, vbase, ubase + r, lane);
         wave_sync_lds();
