@@ -44,7 +44,8 @@ static int is_ballot(int s) { return s == VRO_STATIC_BALLOT || s == VRO_DYN_BALL
 static uint32_t max_batch_tris(int s)
 {
     switch (s) {
-    case VRO_NAIVE: return 0xFFFFFFFFu;
+    case VRO_NAIVE:
+    case VRO_MULTI: return 0xFFFFFFFFu;
     case VRO_STATIC_BALLOT: return 1024;
     case VRO_STATIC_SORT:
     case VRO_STATIC_HASH: return 256;
@@ -54,6 +55,7 @@ static uint32_t max_batch_tris(int s)
 
 uint64_t vro_units_bound(int strategy, uint64_t num_tris, uint32_t batch_tris)
 {
+    if (strategy == VRO_MULTI) return 1;
     if (strategy == VRO_STATIC_SORT || strategy == VRO_STATIC_HASH)
         return batch_tris ? (num_tris + batch_tris - 1) / batch_tris : 0;
     return num_tris;
@@ -63,10 +65,11 @@ int vro_check_args(uint64_t num_indices, uint32_t num_vertices, const vro_shader
                    int strategy, uint32_t batch_tris, const vro_opts *opts,
                    const vro_outputs *out, uint32_t *resolved_max_unique)
 {
-    (void)num_vertices;
     if (!sh || !out) return VRO_ERR_ARG;
     if (num_indices % 3 != 0 || num_indices > 3ull * ((1ull << 30) - 1)) return VRO_ERR_ARG;
-    if (strategy < VRO_NAIVE || strategy > VRO_DYN_BALLOT) return VRO_ERR_ARG;
+    if (strategy < VRO_NAIVE || strategy > VRO_MULTI) return VRO_ERR_ARG;
+    /* MULTI's unit is the whole vertex buffer: no 16-bit local ids */
+    if (strategy == VRO_MULTI && out && out->local_idx) return VRO_ERR_ARG;
     if (batch_tris == 0 || batch_tris > max_batch_tris(strategy)) return VRO_ERR_ARG;
     if (sh->kind > 2 || sh->num_lights > VRO_MAX_LIGHTS || sh->spec_squarings > 8 ||
         sh->iterations > 4096)
@@ -90,7 +93,8 @@ int vro_check_args(uint64_t num_indices, uint32_t num_vertices, const vro_shader
         if ((slots & (slots - 1)) != 0 || slots < need || slots > 4096) return VRO_ERR_ARG;
     }
     uint64_t T = num_indices / 3;
-    if (out->verts && out->verts_cap < 3 * T) return VRO_ERR_CAPACITY;
+    if (out->verts && out->verts_cap < (strategy == VRO_MULTI ? (uint64_t)num_vertices : 3 * T))
+        return VRO_ERR_CAPACITY;
     if ((out->unit_offsets || out->unit_invocations) &&
         out->units_cap < vro_units_bound(strategy, T, batch_tris))
         return VRO_ERR_CAPACITY;
@@ -374,6 +378,31 @@ static int cmp_u32(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
+/* The non-streaming reference of Section 4.2 (Table 2): a first pass
+ * shades every vertex of the vertex buffer once, referenced or not, and a
+ * second pass assembles each corner from the shaded buffer.  The draw is a
+ * single unit whose local ids are the vertex indices themselves. */
+static int multi_draw(const uint32_t *idx, uint64_t T, const float *vertices, uint32_t V,
+                      const vro_shader *sh, uint64_t U, vro_outputs *out)
+{
+    float *shaded = (float *)malloc(sizeof(float) * VRO_OUT_FLOATS * (V ? V : 1));
+    if (!shaded) { set_counters(out, 0, 0, 0, VRO_ERR_ARG); return VRO_ERR_ARG; }
+    for (uint32_t v = 0; v < V; ++v)
+        vro_shade(sh, vertices + (uint64_t)VRO_IN_FLOATS * v, shaded + (uint64_t)VRO_OUT_FLOATS * v);
+    if (out->verts) memcpy(out->verts, shaded, sizeof(float) * VRO_OUT_FLOATS * V);
+    for (uint64_t k = 0; k < 3 * T; ++k) {
+        if (out->tris) out->tris[k] = idx[k];
+        if (out->corners)
+            memcpy(out->corners + VRO_OUT_FLOATS * k, shaded + (uint64_t)VRO_OUT_FLOATS * idx[k],
+                   sizeof(float) * VRO_OUT_FLOATS);
+    }
+    if (out->unit_offsets) { out->unit_offsets[0] = 0; out->unit_offsets[1] = (uint32_t)T; }
+    if (out->unit_invocations) out->unit_invocations[0] = V;
+    free(shaded);
+    set_counters(out, V, 1, U, VRO_OK);
+    return VRO_OK;
+}
+
 int vro_process_draw(const uint32_t *idx, uint64_t num_indices, const float *vertices,
                      uint32_t V, const vro_shader *sh, int strategy, uint32_t batch_tris,
                      const vro_opts *opts, vro_outputs *out)
@@ -390,6 +419,8 @@ int vro_process_draw(const uint32_t *idx, uint64_t num_indices, const float *ver
         set_counters(out, 0, 0, 0, VRO_OK);
         return VRO_OK;
     }
+
+    if (strategy == VRO_MULTI) return multi_draw(idx, T, vertices, V, sh, (uint64_t)U, out);
 
     /* 1. Partition the triangles into units (whole triangles only). */
     stamp_set set;

@@ -41,7 +41,8 @@ enum {
     VRO_DYN_SORT = 4,         /* dynamic batches, ascending-rank ids       */
     VRO_DYN_HASH = 5,         /* dynamic batches, first-occurrence ids     */
     VRO_DYN_PHASH = 6,        /* dynamic batches, first-occurrence ids     */
-    VRO_DYN_BALLOT = 7        /* dynamic batches split into ballot rounds  */
+    VRO_DYN_BALLOT = 7,       /* dynamic batches split into ballot rounds  */
+    VRO_MULTI = 8             /* two passes: shade all V, then assemble    */
 };
 
 #define VRO_WAVE 64           /* distinct-index capacity of a ballot round */
@@ -75,7 +76,7 @@ typedef struct {
     float *corners;           /* [3T][12] or NULL                          */
     uint32_t *tris;           /* [3T] indices into verts, or NULL          */
     float *verts;             /* [verts_cap][12] or NULL                   */
-    uint64_t verts_cap;       /* >= 3T when verts != NULL                  */
+    uint64_t verts_cap;       /* >= 3T (MULTI: >= V) when verts != NULL    */
     uint16_t *local_idx;      /* [3T] unit-local ids, or NULL              */
     uint32_t *unit_offsets;   /* [units_cap + 1] triangle offsets, or NULL */
     uint32_t *unit_invocations; /* [units_cap] or NULL                     */

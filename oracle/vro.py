@@ -15,9 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvro.so")
 
 OK, ERR_ARG, ERR_INDEX_RANGE, ERR_CAPACITY = 0, 1, 2, 3
-NAIVE, STATIC_BALLOT, STATIC_SORT, STATIC_HASH, DYN_SORT, DYN_HASH, DYN_PHASH, DYN_BALLOT = range(8)
+NAIVE, STATIC_BALLOT, STATIC_SORT, STATIC_HASH, DYN_SORT, DYN_HASH, DYN_PHASH, DYN_BALLOT, MULTI = range(9)
 STRATEGY_NAMES = ["naive", "static_ballot", "static_sort", "static_hash", "dyn_sort", "dyn_hash",
-                  "dyn_phash", "dyn_ballot"]
+                  "dyn_phash", "dyn_ballot", "multi"]
 OUT_FLOATS = 12
 
 
@@ -114,8 +114,11 @@ def process_draw(indices, vertices, shader, strategy, batch_tris, opts=None, *,
         res["corners"] = np.zeros((n, OUT_FLOATS), dtype=np.float32)
     if tris:
         res["tris"] = np.zeros(n, dtype=np.uint32)
+    vcap = max(n, V) if strategy == MULTI else n
     if verts:
-        res["verts"] = np.zeros((max(n, 1), OUT_FLOATS), dtype=np.float32)
+        res["verts"] = np.zeros((max(vcap, 1), OUT_FLOATS), dtype=np.float32)
+    if local_idx and strategy == MULTI:
+        local_idx = False   # not defined for the single vertex-buffer unit
     if local_idx:
         res["local_idx"] = np.zeros(n, dtype=np.uint16)
     ucap = units_bound(strategy, T, batch_tris) if batch_tris else T
@@ -124,7 +127,7 @@ def process_draw(indices, vertices, shader, strategy, batch_tris, opts=None, *,
         res["unit_invocations"] = np.zeros(max(ucap, 1), dtype=np.uint32)
     res["counters"] = np.zeros(4, dtype=np.uint64)
     out = Outputs(_ptr(res.get("corners")), _ptr(res.get("tris")), _ptr(res.get("verts")),
-                  n if verts else 0, _ptr(res.get("local_idx")), _ptr(res.get("unit_offsets")),
+                  vcap if verts else 0, _ptr(res.get("local_idx")), _ptr(res.get("unit_offsets")),
                   _ptr(res.get("unit_invocations")), ucap if units else 0, _ptr(res["counters"]))
     sh = shader if isinstance(shader, Shader) else make_shader(shader)
     op = opts if (opts is None or isinstance(opts, Opts)) else make_opts(**opts)

@@ -250,7 +250,7 @@ def test_argument_errors():
     v = np.zeros((1, 8), np.float32)
     sp = _identity_shader()
     assert vro.process_draw(idx[:5], v, sp, vro.NAIVE, 1)[0] == vro.ERR_ARG          # not triangles
-    assert vro.process_draw(idx, v, sp, 8, 1)[0] == vro.ERR_ARG                      # strategy
+    assert vro.process_draw(idx, v, sp, 9, 1)[0] == vro.ERR_ARG                      # strategy
     assert vro.process_draw(idx, v, sp, vro.STATIC_SORT, 0)[0] == vro.ERR_ARG        # batch 0
     assert vro.process_draw(idx, v, sp, vro.STATIC_SORT, 257)[0] == vro.ERR_ARG      # batch cap
     assert vro.process_draw(idx, v, sp, vro.DYN_HASH, 64, {"max_unique": 2})[0] == vro.ERR_ARG
@@ -390,6 +390,49 @@ def test_corners_equal_naive_shading_all_strategies():
         np.testing.assert_array_equal(r["verts"][r["tris"]], ref)
         inv, U = int(r["counters"][0]), int(r["counters"][2])
         assert U <= inv <= len(m.indices)
+
+
+def test_multi_two_pass_reference():
+    """The two-pass reference (Section 4.2, Table 2): every vertex of the
+    buffer is shaded once, referenced or not, and corners are gathered from
+    the shaded buffer.  Pins: invocations are V (not U), the shaded list is
+    the buffer in vertex order, the assembled indices are the input indices,
+    one unit spans the draw, and the corners equal naive shading bitwise."""
+    m = W.grid_mesh(9, 7, 5, "hilbert")
+    rng = np.random.default_rng(3)
+    extra = rng.random((13, 8), dtype=np.float32)                # 13 unreferenced vertices
+    vb = np.concatenate([m.vertices, extra])
+    sp = W.shader_for_mesh(m, W.SHADER_PHONG, 2, num_lights=3)
+    rc, r = vro.process_draw(m.indices, vb, sp, vro.MULTI, 1)
+    assert rc == vro.OK
+    V, U, T = len(vb), len(np.unique(m.indices)), m.num_tris
+    assert r["counters"].tolist() == [V, 1, U, 0]
+    np.testing.assert_array_equal(r["verts"], vro.shade(sp, vb))
+    np.testing.assert_array_equal(r["tris"], m.indices)
+    assert r["unit_offsets"].tolist() == [0, T] and r["unit_invocations"].tolist() == [V]
+    rc, nv = vro.process_draw(m.indices, vb, sp, vro.NAIVE, 1)
+    np.testing.assert_array_equal(r["corners"], nv["corners"])
+    # an empty draw shades nothing
+    rc, e = vro.process_draw(np.zeros(0, np.uint32), vb, sp, vro.MULTI, 1)
+    assert rc == vro.OK and e["counters"].tolist() == [0, 0, 0, 0]
+
+
+def test_multi_argument_rules():
+    """Local ids are not defined for the single buffer-sized unit, and the
+    shaded list needs room for all V vertices, not 3T."""
+    import ctypes as C
+    idx = np.array([0, 1, 2], np.uint32)
+    sh = vro.make_shader(_identity_shader())
+    lid = np.zeros(3, np.uint16)
+    verts = np.zeros((8, 12), np.float32)
+    def check(local, vcap):
+        out = vro.Outputs(None, None, verts.ctypes.data, vcap, lid.ctypes.data if local else None, None, None, 0,
+                          None)
+        return vro.lib().vro_check_args(3, 8, C.byref(sh), vro.MULTI, 1, None, C.byref(out), None)
+    assert check(False, 8) == vro.OK
+    assert check(True, 8) == vro.ERR_ARG
+    assert check(False, 7) == vro.ERR_CAPACITY     # 3T = 3 would do for the batched strategies
+    assert vro.units_bound(vro.MULTI, 1000, 1) == 1
 
 
 def test_plan_of_a_prefix_is_the_cut_plan():
