@@ -234,7 +234,7 @@ def measure_draw(stage, idx, vtx, V, sp, strategy, bt, nu=0, reps=20, flush=None
             stage.check(vr.vr_plan_dynamic(stage.ctx, idx, V, nu, bt, plan))
         plan_ms = float(np.median(vr.vr_kernel_times(stage.ctx)))
         vr.vr_set_kernel_timing(stage.ctx, False)
-    out = stage.alloc_outputs(T, strategy, bt, corners=True)
+    out = stage.alloc_outputs(T, strategy, bt, corners=True, num_vertices=V)
     o = vr.make_opts(max_unique=nu, plan=plan)
     for _ in range(3):
         stage.check(vr.vr_process_draw(stage.ctx, idx, vtx, sh, strategy, bt, o, stage.describe(out)))
@@ -259,6 +259,8 @@ def measure_draw(stage, idx, vtx, V, sp, strategy, bt, nu=0, reps=20, flush=None
     U = int(V)
     k = float(np.median(kms))
     alg = 12 * T + 32 * min(U, inv) + 144 * T
+    if strategy == vr.VR_MULTI:   # the shaded buffer is written once and read back at least once
+        alg = 12 * T + 32 * U + 96 * U + 144 * T
     return {"batch_tris": bt, "max_unique": nu, "kernel_ms_p50": k, "draw_ms_p50": float(np.percentile(ms, 50)),
             "draw_ms_p99": float(np.percentile(ms, 99)), "plan_ms_p50": plan_ms, "invocations": inv,
             "reuse": 1.0 - inv / (3.0 * T), "tri_per_s": T / (k * 1e-3),
@@ -593,6 +595,13 @@ def main():
         del flush
         torch.cuda.empty_cache()
         progress("cold runs done")
+    multi = None
+    if not args.only and not args.no_extra:
+        # the two-pass reference (shade the vertex buffer, then gather)
+        multi = measure_draw(stage, idx, vtx, V, sp, vr.VR_MULTI, 1, reps=20)
+        multi["speedup_vs_naive"] = per["naive"]["kernel_ms_mean"] / multi["kernel_ms_p50"]
+        multi["dyn_hash_speedup"] = multi["kernel_ms_p50"] / per["dyn_hash"]["kernel_ms_mean"]
+        progress("two-pass reference done")
     plain = heavy = None
     if not args.only and not args.no_extra:
         try:
@@ -621,7 +630,7 @@ def main():
                        "unique_vertices": U, "strategies": [s[0] for s in strategies],
                        "static_batch_tris": 64, "dynamic_max_unique": NU, "dynamic_max_tris": NP,
                        "output": "per-corner shaded vertices + invocation counters"},
-            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "cold": cold, "plain": plain, "heavy": heavy, "scene": scene,
+            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "multi": multi, "cold": cold, "plain": plain, "heavy": heavy, "scene": scene,
             "serving": serving}
     print(json.dumps(line), flush=True)
     stage.close()

@@ -74,6 +74,15 @@ typedef enum {
  *                 wavefront-cooperative probing (Section 3.4, "parallel
  *                 hashing"); ids in first-occurrence order.
  *  DYN_BALLOT     dynamic batches cut into ballot rounds as STATIC_BALLOT.
+ *  MULTI          the non-streaming two-pass reference of Section 4.2
+ *                 (Table 2): one kernel shades every vertex of the buffer
+ *                 once, referenced or not (invocations = num_vertices), a
+ *                 second gathers the corners from the shaded buffer.  One
+ *                 unit spans the draw; its local ids are the vertex indices,
+ *                 so tris = indices and verts holds all num_vertices shaded
+ *                 vertices in buffer order.  batch_tris is ignored (>= 1);
+ *                 local_idx is not available (VR_ERR_ARG); not accepted in
+ *                 frames or by the server.
  * Hash-table slot numbers depend on atomic races; exported ids never do.
  */
 typedef enum {
@@ -84,7 +93,8 @@ typedef enum {
     VR_DYN_SORT = 4,
     VR_DYN_HASH = 5,
     VR_DYN_PHASH = 6,
-    VR_DYN_BALLOT = 7
+    VR_DYN_BALLOT = 7,
+    VR_MULTI = 8
 } vr_strategy;
 
 /* Limits on batch_tris per strategy (argument error beyond them). */
@@ -133,12 +143,14 @@ typedef struct {
  *                    into verts.
  *  verts             float[verts_cap][12]: unit u's shaded vertices at rows
  *                    vbase(u) .. vbase(u)+inv(u)-1, vbase = sum of earlier
- *                    units' invocations.  verts_cap >= 3T when verts != NULL.
+ *                    units' invocations.  verts_cap >= 3T (MULTI: >= num_vertices)
+ *                    when verts != NULL.
  *  local_idx         uint16[3T]: the unit-local id of every corner.
  *  unit_offsets      uint32[units_cap+1]: first triangle of every unit, then T.
  *  unit_invocations  uint32[units_cap]: vertex-shader invocations per unit.
  *                    units_cap >= T, or >= ceil(T/batch_tris) for
- *                    STATIC_SORT / STATIC_HASH, when either unit array is set.
+ *                    STATIC_SORT / STATIC_HASH, or >= 1 for MULTI, when
+ *                    either unit array is set.
  *  counters          uint64[4]: {invocations, units, 0, 0}, overwritten.
  */
 typedef struct {

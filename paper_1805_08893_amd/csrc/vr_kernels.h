@@ -233,6 +233,60 @@ __global__ __launch_bounds__(256) void k_naive(DrawArgs A, vr_shader_params sh) 
 }
 
 // ---------------------------------------------------------------------------
+// Two-pass reference (Section 4.2, Table 2), not streaming: every vertex of
+// the buffer is shaded once by a first kernel, referenced or not; a second
+// kernel assembles the corners from the shaded buffer in global memory.
+// ---------------------------------------------------------------------------
+// 256 vertices per workgroup: shaded into LDS, then stored as one contiguous
+// span of rows (plain stores, so the rows stay in the caches for the gather).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_multi_shade(DrawArgs A, vr_shader_params sh, f4 *shaded) {
+    __shared__ f4 s_sv[256 * 3];
+    const uint32_t v0 = blockIdx.x * 256, tid = threadIdx.x;
+    const uint32_t cnt = min(256u, A.V - v0);
+    if (tid < cnt) shade_to_lds<KIND>(A, sh, v0 + tid, s_sv + 3 * tid);
+    __syncthreads();
+    f4 *dst = shaded + 3ull * v0;
+    for (uint32_t q = tid; q < 3 * cnt; q += 256) dst[q] = s_sv[q];
+}
+
+// 256 corners per workgroup: each lane gathers its corner's three rows from
+// the shaded buffer into LDS, then the block's rows are stored as one
+// contiguous span (fully coalesced 16-byte stores).  The single unit's
+// counters and offsets come from block 0.
+__global__ __launch_bounds__(256) void k_multi_assemble(DrawArgs A, const f4 *shaded) {
+    __shared__ f4 s_rows[256 * 3];
+    const uint64_t n = 3ull * A.T, c0 = (uint64_t)blockIdx.x * 256;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(256, n - c0);
+    if (tid < cnt) {
+        const uint32_t v = fetch_index(A, c0 + tid);
+        const f4 *src = shaded + 3ull * v;
+        s_rows[3 * tid] = src[0];
+        s_rows[3 * tid + 1] = src[1];
+        s_rows[3 * tid + 2] = src[2];
+        if (A.tris) A.tris[c0 + tid] = v;
+    }
+    __syncthreads();
+    if (A.corners)
+        for (uint32_t q = tid; q < 3 * cnt; q += 256) __builtin_nontemporal_store(s_rows[q], A.corners + 3 * c0 + q);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (A.counters) {
+            A.counters[0] = A.V;
+            A.counters[1] = 1;
+            A.counters[2] = 0;
+            A.counters[3] = 0;
+        }
+        if (A.unit_offsets) {
+            A.unit_offsets[0] = 0;
+            A.unit_offsets[1] = A.T;
+        }
+        if (A.unit_inv) A.unit_inv[0] = A.V;
+        atomicAdd(A.total_inv, (unsigned long long)A.V);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // LDS layout of the dedup kernel (bytes), shared with the host launcher.
 // ---------------------------------------------------------------------------
 struct DedupLds {

@@ -51,7 +51,7 @@ struct vr_ctx {
     size_t lds_limit = 65536;
     std::string error;
     CtxWords *d_words = nullptr;
-    Scratch status, agg, plan, plan_work, tune;
+    Scratch status, agg, plan, plan_work, tune, shaded;   // shaded: MULTI's vertex pass
     uint32_t host_err = 0;   // data error found on the host, reported by vr_sync
     uint32_t plan_epoch = 0;  // numbers planning calls (0 is never used)
     bool timing = false;
@@ -139,7 +139,8 @@ bool is_ballot(vr_strategy s) { return s == VR_STATIC_BALLOT || s == VR_DYN_BALL
 
 uint32_t batch_limit(vr_strategy s) {
     switch (s) {
-    case VR_NAIVE: return 0xFFFFFFFFu;
+    case VR_NAIVE:
+    case VR_MULTI: return 0xFFFFFFFFu;
     case VR_STATIC_BALLOT: return VR_MAX_BATCH_BALLOT;
     case VR_STATIC_SORT:
     case VR_STATIC_HASH: return VR_MAX_BATCH_STATIC;
@@ -152,6 +153,7 @@ uint32_t default_max_unique(uint32_t batch_tris) {
 }
 
 uint64_t units_bound(vr_strategy s, uint64_t T, uint32_t batch_tris) {
+    if (s == VR_MULTI) return 1;
     if (s == VR_STATIC_SORT || s == VR_STATIC_HASH) return (T + batch_tris - 1) / batch_tris;
     return T;
 }
@@ -173,13 +175,16 @@ struct Resolved {
     uint32_t nu = 0, nt = 0, max_idx = 0, max_uniq = 0, hash_bits = 0, probes = 4;
 };
 
-vr_status check_args(vr_ctx *c, uint64_t num_indices, const vr_shader_params *sh, vr_strategy strategy,
-                     uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out, Resolved *res) {
+vr_status check_args(vr_ctx *c, uint64_t num_indices, uint32_t num_vertices, const vr_shader_params *sh,
+                     vr_strategy strategy, uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out,
+                     Resolved *res) {
     if (!sh || !out) return fail(c, VR_ERR_ARG, "shader and outputs must not be NULL");
     if (num_indices % 3 != 0) return fail(c, VR_ERR_ARG, "num_indices %llu is not a multiple of 3",
                                           (unsigned long long)num_indices);
     if (num_indices > VR_MAX_INDICES) return fail(c, VR_ERR_ARG, "more than 2^30-1 triangles");
-    if ((int)strategy < 0 || strategy > VR_DYN_BALLOT) return fail(c, VR_ERR_ARG, "unknown strategy %d", (int)strategy);
+    if ((int)strategy < 0 || strategy > VR_MULTI) return fail(c, VR_ERR_ARG, "unknown strategy %d", (int)strategy);
+    if (strategy == VR_MULTI && out->local_idx)
+        return fail(c, VR_ERR_ARG, "MULTI has no unit-local ids (its unit is the whole vertex buffer)");
     if (batch_tris == 0 || batch_tris > batch_limit(strategy))
         return fail(c, VR_ERR_ARG, "batch_tris %u outside 1..%u for this strategy", batch_tris, batch_limit(strategy));
     if (sh->kind > 2) return fail(c, VR_ERR_ARG, "unknown shader kind %u", sh->kind);
@@ -201,20 +206,22 @@ vr_status check_args(vr_ctx *c, uint64_t num_indices, const vr_shader_params *sh
         r.max_idx = 3 * batch_tris;
         r.max_uniq = 3 * batch_tris;
     }
-    if (strategy == VR_NAIVE) r.max_idx = r.max_uniq = 3;
+    if (strategy == VR_NAIVE || strategy == VR_MULTI) r.max_idx = r.max_uniq = 3;
     if (o.hash_slots != 0) {
         const uint32_t need = is_dynamic(strategy) ? r.nu : 3u * batch_tris;
         if ((o.hash_slots & (o.hash_slots - 1)) != 0 || o.hash_slots < need || o.hash_slots > 4096)
             return fail(c, VR_ERR_ARG, "hash_slots %u: need a power of two in %u..4096", o.hash_slots, need);
     }
     const uint64_t T = num_indices / 3;
-    if (out->verts && out->verts_cap < 3 * T)
-        return fail(c, VR_ERR_CAPACITY, "verts_cap %llu < 3T", (unsigned long long)out->verts_cap);
+    const uint64_t vneed = strategy == VR_MULTI ? (uint64_t)num_vertices : 3 * T;
+    if (out->verts && out->verts_cap < vneed)
+        return fail(c, VR_ERR_CAPACITY, "verts_cap %llu < %llu", (unsigned long long)out->verts_cap,
+                    (unsigned long long)vneed);
     if ((out->unit_offsets || out->unit_invocations) && out->units_cap < units_bound(strategy, T, batch_tris))
         return fail(c, VR_ERR_CAPACITY, "units_cap %llu below the bound %llu", (unsigned long long)out->units_cap,
                     (unsigned long long)units_bound(strategy, T, batch_tris));
     // launch shape (never changes results)
-    if (strategy != VR_NAIVE && !is_ballot(strategy)) {
+    if (strategy != VR_NAIVE && strategy != VR_MULTI && !is_ballot(strategy)) {
         uint32_t want = o.wg_size ? o.wg_size : std::max<uint32_t>(64, std::min<uint32_t>(256, r.max_uniq));
         uint32_t nt = 64;
         while (nt * 2 <= want && nt < 512) nt *= 2;
@@ -453,8 +460,10 @@ vr_status describe_draw(vr_ctx *c, const vr_draw &D, const vr_shader_params &sh,
     ov.corners = D.d_corners;
     ov.counters = D.d_counters;
     Resolved r;
-    vr_status st = check_args(c, D.num_indices, &sh, D.strategy, D.batch_tris, &o, &ov, &r);
+    vr_status st = check_args(c, D.num_indices, D.num_vertices, &sh, D.strategy, D.batch_tris, &o, &ov, &r);
     if (st != VR_OK) return fail(c, st, "draw %u: %s", d, c->error.c_str());
+    if (D.strategy == VR_MULTI)
+        return fail(c, VR_ERR_ARG, "draw %u: MULTI (two passes over the vertex buffer) cannot join a frame", d);
     const uint64_t T = D.num_indices / 3;
     if (T && (!D.d_indices || !D.d_vertices || !D.d_corners))
         return fail(c, VR_ERR_ARG, "draw %u: indices, vertices and corners are required", d);
@@ -533,7 +542,7 @@ void vr_destroy(vr_ctx *c) {
     if (!c) return;
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (Scratch *s : {&c->status, &c->agg, &c->plan, &c->plan_work, &c->tune})
+    for (Scratch *s : {&c->status, &c->agg, &c->plan, &c->plan_work, &c->tune, &c->shaded})
         if (s->ptr) (void)hipFree(s->ptr);
     for (auto &pr : c->ev_pool) {
         (void)hipEventDestroy(pr.first);
@@ -552,7 +561,7 @@ vr_status vr_set_stream(vr_ctx *c, void *hip_stream) {
 vr_status vr_check_args(uint64_t num_indices, uint32_t num_vertices, const vr_shader_params *shader,
                         vr_strategy strategy, uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out) {
     (void)num_vertices;
-    return check_args(nullptr, num_indices, shader, strategy, batch_tris, opts, out, nullptr);
+    return check_args(nullptr, num_indices, num_vertices, shader, strategy, batch_tris, opts, out, nullptr);
 }
 
 vr_status vr_plan_dynamic(vr_ctx *c, const uint32_t *d_indices, uint64_t num_indices, uint32_t num_vertices,
@@ -578,7 +587,7 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
                           uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out) {
     if (!c) return VR_ERR_ARG;
     Resolved r;
-    vr_status st = check_args(c, num_indices, shader, strategy, batch_tris, opts, out, &r);
+    vr_status st = check_args(c, num_indices, num_vertices, shader, strategy, batch_tris, opts, out, &r);
     if (st != VR_OK) return st;
     const uint64_t T = num_indices / 3;
     if (T && (!d_indices || !d_vertices)) return fail(c, VR_ERR_ARG, "indices or vertices are NULL");
@@ -619,6 +628,22 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
     A.need_prefix = (out->tris || out->verts || out->unit_offsets || out->unit_invocations) ? 1u : 0u;
 
     const vr_shader_params &sh = *shader;
+    if (strategy == VR_MULTI) {
+        f4 *shaded = (f4 *)out->verts;
+        if (!shaded) {
+            st = ensure(c, c->shaded, 48ull * num_vertices);
+            if (st != VR_OK) return st;
+            shaded = (f4 *)c->shaded.ptr;
+        }
+        TimedRegion timed(c);
+        const dim3 gs((num_vertices + 255) / 256), ga((uint32_t)((3ull * T + 255) / 256));
+        if (sh.kind == 0) hipLaunchKernelGGL(k_multi_shade<0>, gs, dim3(256), 0, c->stream, A, sh, shaded);
+        else if (sh.kind == 1) hipLaunchKernelGGL(k_multi_shade<1>, gs, dim3(256), 0, c->stream, A, sh, shaded);
+        else hipLaunchKernelGGL(k_multi_shade<2>, gs, dim3(256), 0, c->stream, A, sh, shaded);
+        hipLaunchKernelGGL(k_multi_assemble, ga, dim3(256), 0, c->stream, A, (const f4 *)shaded);
+        VR_HIP(c, hipGetLastError());
+        return VR_OK;
+    }
     if (strategy == VR_NAIVE) {
         TimedRegion timed(c);
         if (sh.kind == 0) launch_naive<0>(c, A, sh);
@@ -844,7 +869,7 @@ vr_status vr_autotune(vr_ctx *c, const uint32_t *d_idx, uint64_t num_indices, co
         out.corners = corners;
         out.counters = counters;
         Resolved r;
-        if (check_args(c, num_indices, sh, k.strategy, k.batch_tris, &o, &out, &r) != VR_OK) continue;
+        if (check_args(c, num_indices, V, sh, k.strategy, k.batch_tris, &o, &out, &r) != VR_OK) continue;
         if (is_dynamic(k.strategy)) {
             (void)hipEventRecord(e0, c->stream);
             if (vr_plan_dynamic(c, d_idx, num_indices, V, r.nu, k.batch_tris, plan, T + 2) != VR_OK) continue;
@@ -1325,8 +1350,10 @@ vr_status vr_server_submit(vr_server *s, const vr_request *r, uint64_t *ticket) 
     o.max_unique = r->max_unique;
     vr_outputs ov{};
     Resolved res;
-    if (check_args(s->ctx, 3ull * r->num_tris, &r->shader, r->strategy, r->batch_tris, &o, &ov, &res) != VR_OK)
+    if (check_args(s->ctx, 3ull * r->num_tris, M.V, &r->shader, r->strategy, r->batch_tris, &o, &ov, &res) != VR_OK)
         return server_fail(s, VR_ERR_ARG, "%s", s->ctx->error.c_str());
+    if (r->strategy == VR_MULTI)
+        return server_fail(s, VR_ERR_ARG, "MULTI (two passes over the vertex buffer) is not served");
     R.nu = is_dynamic(r->strategy) ? res.nu : 0;
     FrameNeeds need;
     DrawDesc X;

@@ -19,10 +19,10 @@ LIB_PATH = os.path.join(HERE, "libvr.so")
 (VR_OK, VR_ERR_ARG, VR_ERR_INDEX_RANGE, VR_ERR_CAPACITY, VR_ERR_OOM, VR_ERR_DEVICE, VR_ERR_BUSY,
  VR_CANCELLED) = range(8)
 (VR_NAIVE, VR_STATIC_BALLOT, VR_STATIC_SORT, VR_STATIC_HASH, VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH,
- VR_DYN_BALLOT) = range(8)
+ VR_DYN_BALLOT, VR_MULTI) = range(9)
 STRATEGIES = {"naive": VR_NAIVE, "static_ballot": VR_STATIC_BALLOT, "static_sort": VR_STATIC_SORT,
               "static_hash": VR_STATIC_HASH, "dyn_sort": VR_DYN_SORT, "dyn_hash": VR_DYN_HASH,
-              "dyn_phash": VR_DYN_PHASH, "dyn_ballot": VR_DYN_BALLOT}
+              "dyn_phash": VR_DYN_PHASH, "dyn_ballot": VR_DYN_BALLOT, "multi": VR_MULTI}
 STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 DYNAMIC = (VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH, VR_DYN_BALLOT)
 OUT_FLOATS = 12
@@ -325,7 +325,8 @@ class GeometryStage:
             raise VrError(st, vr_last_error(self.ctx))
 
     def alloc_outputs(self, num_tris, strategy, batch_tris, corners=True, tris=False, verts=False,
-                      local_idx=False, units=False):
+                      local_idx=False, units=False, num_vertices=0):
+        """Output tensors for a draw; MULTI's verts hold all num_vertices."""
         torch = self.torch
         n = 3 * num_tris
         res = {"counters": torch.zeros(4, dtype=torch.int64, device=self.device)}
@@ -334,7 +335,8 @@ class GeometryStage:
         if tris:
             res["tris"] = torch.empty(n, dtype=torch.int32, device=self.device)
         if verts:
-            res["verts"] = torch.empty((max(n, 1), OUT_FLOATS), dtype=torch.float32, device=self.device)
+            rows = max(n, num_vertices) if strategy == VR_MULTI else n
+            res["verts"] = torch.empty((max(rows, 1), OUT_FLOATS), dtype=torch.float32, device=self.device)
         if local_idx:
             res["local_idx"] = torch.empty(n, dtype=torch.int16, device=self.device)
         if units:
@@ -367,6 +369,8 @@ class GeometryStage:
 
 
 def units_bound(strategy, num_tris, batch_tris):
+    if strategy == VR_MULTI:
+        return 1
     if strategy in (VR_STATIC_SORT, VR_STATIC_HASH):
         return (num_tris + batch_tris - 1) // batch_tris
     return num_tris

@@ -43,7 +43,12 @@ def _cases():
     yield "ok_empty", dict(n=0, strategy=vr.VR_DYN_SORT, bt=64)
     yield "not_triangles", dict(n=301, strategy=vr.VR_NAIVE, bt=1)
     yield "too_many", dict(n=3 * (1 << 30), strategy=vr.VR_NAIVE, bt=1)
-    yield "bad_strategy", dict(n=300, strategy=8, bt=1)
+    yield "bad_strategy", dict(n=300, strategy=9, bt=1)
+    yield "ok_multi", dict(n=300, strategy=vr.VR_MULTI, bt=1)
+    yield "multi_verts_cap", dict(n=300, strategy=vr.VR_MULTI, bt=1, verts_cap=99)        # V = 100
+    yield "multi_verts_cap_ok", dict(n=300, strategy=vr.VR_MULTI, bt=1, verts_cap=100)    # below 3T
+    yield "multi_units_cap_ok", dict(n=300, strategy=vr.VR_MULTI, bt=1, units_cap=1)
+    yield "multi_local_idx", dict(n=300, strategy=vr.VR_MULTI, bt=1, local=True)
     yield "batch0", dict(n=300, strategy=vr.VR_STATIC_HASH, bt=0)
     yield "static_cap", dict(n=300, strategy=vr.VR_STATIC_HASH, bt=257)
     yield "ballot_cap_ok", dict(n=300, strategy=vr.VR_STATIC_BALLOT, bt=1024)
@@ -75,9 +80,10 @@ def test_argument_rules_match_oracle(name, case):
     dummy = 0x1000
     vcap = case.get("verts_cap")
     ucap = case.get("units_cap")
-    o_out = vro.Outputs(None, None, dummy if vcap is not None else None, vcap or 0, None,
+    loc = dummy if case.get("local") else None
+    o_out = vro.Outputs(None, None, dummy if vcap is not None else None, vcap or 0, loc,
                         dummy if ucap is not None else None, None, ucap or 0, None)
-    g_out = vr.vr_outputs(None, None, dummy if vcap is not None else None, vcap or 0, None,
+    g_out = vr.vr_outputs(None, None, dummy if vcap is not None else None, vcap or 0, loc,
                           dummy if ucap is not None else None, None, ucap or 0, None)
     o_sh = vro.make_shader(sp)
     st_o = vro.lib().vro_check_args(case["n"], 100, C.byref(o_sh), case["strategy"], case["bt"], C.byref(o_opts),
