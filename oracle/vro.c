@@ -147,6 +147,123 @@ int64_t vro_fifo_misses(const uint32_t *idx, uint64_t n, uint32_t V, uint32_t k)
     return misses;
 }
 
+/* Parallel per-processor LRU post-transform caches (Section 4.1, Table 1).
+ * The index stream is cut into chunks of `per_cycle` indices.  With
+ * contiguous != 0 the chunks are split into `procs` consecutive runs of
+ * ceil(chunks / procs), run p on processor p, one chunk per shading cycle;
+ * otherwise chunk c runs on processor c mod procs in its cycle c / procs.
+ * A processor looks
+ * every index of its chunk up in its own LRU cache of `entries` shaded
+ * vertices as the cache stood after its previous cycle: a hit reuses the
+ * result, a miss is shaded in this cycle (duplicates inside one chunk are
+ * processed concurrently and all miss).  Then the chunk's indices enter the
+ * cache in stream order, each moving to the most-recent end, the least
+ * recently used entry leaving when the cache is full.  Processors share
+ * nothing, so they are simulated one after another.  Returns the hits, or
+ * -1 for an index >= V or an allocation failure. */
+typedef struct {
+    uint32_t cap, mask, head, tail, size;   /* doubly linked list, most recent at head */
+    uint32_t *key, *prev, *next;            /* per entry                               */
+    uint32_t *slot;                         /* open addressing: entry + 1, 0 = empty   */
+} lru_cache;
+
+static uint32_t lru_hash(uint32_t v, uint32_t mask) { return (v * 2654435761u) & mask; }
+
+static uint32_t lru_find(const lru_cache *c, uint32_t v)   /* entry index or UINT32_MAX */
+{
+    for (uint32_t h = lru_hash(v, c->mask);; h = (h + 1) & c->mask) {
+        if (c->slot[h] == 0) return UINT32_MAX;
+        if (c->key[c->slot[h] - 1] == v) return c->slot[h] - 1;
+    }
+}
+
+static void lru_unlink(lru_cache *c, uint32_t e)
+{
+    if (c->prev[e] != UINT32_MAX) c->next[c->prev[e]] = c->next[e]; else c->head = c->next[e];
+    if (c->next[e] != UINT32_MAX) c->prev[c->next[e]] = c->prev[e]; else c->tail = c->prev[e];
+}
+
+static void lru_push_front(lru_cache *c, uint32_t e)
+{
+    c->prev[e] = UINT32_MAX;
+    c->next[e] = c->head;
+    if (c->head != UINT32_MAX) c->prev[c->head] = e; else c->tail = e;
+    c->head = e;
+}
+
+static void lru_erase_key(lru_cache *c, uint32_t v)   /* backward-shift deletion */
+{
+    uint32_t h = lru_hash(v, c->mask);
+    while (c->key[c->slot[h] - 1] != v) h = (h + 1) & c->mask;
+    for (uint32_t j = (h + 1) & c->mask;; j = (j + 1) & c->mask) {
+        if (c->slot[j] == 0) break;
+        const uint32_t home = lru_hash(c->key[c->slot[j] - 1], c->mask);
+        /* the entry at j may move to h if h lies cyclically in [home, j) */
+        if (((j - home) & c->mask) >= ((j - h) & c->mask)) {
+            c->slot[h] = c->slot[j];
+            h = j;
+        }
+    }
+    c->slot[h] = 0;
+}
+
+static void lru_touch(lru_cache *c, uint32_t v)
+{
+    uint32_t e = lru_find(c, v);
+    if (e != UINT32_MAX) { lru_unlink(c, e); lru_push_front(c, e); return; }
+    if (c->size == c->cap) {                       /* reuse the least recent entry */
+        e = c->tail;
+        lru_unlink(c, e);
+        lru_erase_key(c, c->key[e]);
+    } else {
+        e = c->size++;
+    }
+    c->key[e] = v;
+    uint32_t h = lru_hash(v, c->mask);
+    while (c->slot[h] != 0) h = (h + 1) & c->mask;
+    c->slot[h] = e + 1;
+    lru_push_front(c, e);
+}
+
+int64_t vro_parallel_cache_hits(const uint32_t *idx, uint64_t n, uint32_t V, uint32_t procs, uint32_t per_cycle,
+                                uint32_t entries, int contiguous)
+{
+    for (uint64_t i = 0; i < n; ++i)
+        if (idx[i] >= V) return -1;
+    if (procs == 0 || per_cycle == 0) return -1;
+    if (entries == 0) return 0;
+    uint32_t slots = 2;
+    while (slots < 2 * entries) slots <<= 1;
+    lru_cache c;
+    c.cap = entries;
+    c.mask = slots - 1;
+    c.key = (uint32_t *)malloc(sizeof(uint32_t) * entries);
+    c.prev = (uint32_t *)malloc(sizeof(uint32_t) * entries);
+    c.next = (uint32_t *)malloc(sizeof(uint32_t) * entries);
+    c.slot = (uint32_t *)malloc(sizeof(uint32_t) * slots);
+    if (!c.key || !c.prev || !c.next || !c.slot) {
+        free(c.key); free(c.prev); free(c.next); free(c.slot);
+        return -1;
+    }
+    int64_t hits = 0;
+    const uint64_t chunks = (n + per_cycle - 1) / per_cycle;
+    const uint64_t run = (chunks + procs - 1) / procs;
+    for (uint32_t p = 0; p < procs && p < chunks; ++p) {
+        c.head = c.tail = UINT32_MAX;
+        c.size = 0;
+        memset(c.slot, 0, sizeof(uint32_t) * slots);
+        const uint64_t first = contiguous ? p * run : p, step = contiguous ? 1 : procs;
+        const uint64_t last = contiguous ? (first + run < chunks ? first + run : chunks) : chunks;
+        for (uint64_t ch = first; ch < last; ch += step) {
+            const uint64_t a = ch * per_cycle, b = a + per_cycle < n ? a + per_cycle : n;
+            for (uint64_t i = a; i < b; ++i) hits += lru_find(&c, idx[i]) != UINT32_MAX;
+            for (uint64_t i = a; i < b; ++i) lru_touch(&c, idx[i]);
+        }
+    }
+    free(c.key); free(c.prev); free(c.next); free(c.slot);
+    return hits;
+}
+
 /* Stamp set over vertex ids: membership test in O(1) without clearing. */
 typedef struct {
     uint32_t *stamp;

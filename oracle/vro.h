@@ -117,6 +117,14 @@ int64_t vro_count_unique(const uint32_t *indices, uint64_t n, uint32_t num_verti
  * (Section 2): a hit does not reorder, a miss inserts and evicts the oldest. */
 int64_t vro_fifo_misses(const uint32_t *indices, uint64_t n, uint32_t num_vertices, uint32_t k);
 
+/* Section 4.1, Table 1: hits of `procs` parallel per-processor LRU caches of
+ * `entries` shaded vertices each; chunks of `per_cycle` indices go to the
+ * processors in consecutive runs (contiguous != 0) or round robin; lookups
+ * see the cache as it stood after the processor's previous cycle (no hit
+ * among concurrently shaded duplicates).  -1 on a bad index. */
+int64_t vro_parallel_cache_hits(const uint32_t *indices, uint64_t n, uint32_t num_vertices, uint32_t procs,
+                                uint32_t per_cycle, uint32_t entries, int contiguous);
+
 #ifdef __cplusplus
 }
 #endif

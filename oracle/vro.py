@@ -70,6 +70,8 @@ def lib():
         L.vro_count_unique.restype = C.c_int64
         L.vro_fifo_misses.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32]
         L.vro_fifo_misses.restype = C.c_int64
+        L.vro_parallel_cache_hits.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int]
+        L.vro_parallel_cache_hits.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -167,6 +169,13 @@ def shade(shader, vin, f64=False):
 def count_unique(indices, num_vertices):
     indices = np.ascontiguousarray(indices, dtype=np.uint32)
     return int(lib().vro_count_unique(_ptr(indices), len(indices), num_vertices))
+
+
+def parallel_cache_hits(indices, num_vertices, procs, per_cycle, entries, contiguous=True):
+    """Hits of parallel per-processor LRU caches (Section 4.1, Table 1)."""
+    indices = np.ascontiguousarray(indices, dtype=np.uint32)
+    return int(lib().vro_parallel_cache_hits(_ptr(indices), len(indices), num_vertices, procs, per_cycle, entries,
+                                             1 if contiguous else 0))
 
 
 def fifo_misses(indices, num_vertices, k):

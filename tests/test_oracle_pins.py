@@ -470,3 +470,61 @@ def test_plan_is_the_aligned_chain_when_every_window_fits():
                 cases += 1
                 assert np.array_equal(plan, aligned), (m.name, nu, bt)
     assert cases >= 8
+
+
+# ------------------------------------------------ parallel caches (Table 1)
+def _lru_hits(stream, cap):
+    """Textbook sequential LRU cache of `cap` entries: hits."""
+    from collections import OrderedDict
+    c, hits = OrderedDict(), 0
+    for v in stream:
+        if v in c:
+            hits += 1
+            c.move_to_end(v)
+        else:
+            c[v] = True
+            if len(c) > cap:
+                c.popitem(last=False)
+    return hits
+
+
+def test_parallel_cache_one_processor_is_a_textbook_lru():
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        V = int(rng.integers(2, 40))
+        s = rng.integers(0, V, int(rng.integers(1, 300))).astype(np.uint32)
+        for cap in (1, 2, 5, 17, 64):
+            assert vro.parallel_cache_hits(s, V, 1, 1, cap) == _lru_hits(s.tolist(), cap), (trial, cap)
+    # capacity at least the distinct count: every repeat hits (the ideal reuse)
+    m = W.grid_mesh(12, 10, 2, "hilbert")
+    U = len(np.unique(m.indices))
+    assert vro.parallel_cache_hits(m.indices, m.num_verts, 1, 1, U) == len(m.indices) - U
+    # more capacity never loses a hit (LRU inclusion)
+    h = [vro.parallel_cache_hits(m.indices, m.num_verts, 1, 1, c) for c in (1, 4, 16, 64, 256)]
+    assert h == sorted(h)
+
+
+def test_parallel_cache_concurrency_and_assignment():
+    s = np.array([0, 0, 0, 1, 1, 2], np.uint32)
+    assert vro.parallel_cache_hits(s, 3, 1, 1, 8) == 3
+    assert vro.parallel_cache_hits(s, 3, 1, 6, 8) == 0          # one cycle: every duplicate is concurrent
+    assert vro.parallel_cache_hits(s, 3, 1, 3, 8) == 0          # cycles [0 0 0] [1 1 2]: nothing cached yet
+    assert vro.parallel_cache_hits(np.array([5, 6, 5, 6], np.uint32), 7, 1, 2, 8) == 2
+    m = W.grid_mesh(20, 16, 3, "hilbert")
+    n, V, N = len(m.indices), m.num_verts, 48
+    chunks = -(-n // N)
+    # as many processors as chunks: no processor ever sees a second cycle
+    for contiguous in (True, False):
+        assert vro.parallel_cache_hits(m.indices, V, chunks, N, 64, contiguous) == 0
+    # processors share nothing: the total is the sum over each processor's
+    # own chunk sequence run on one processor
+    P = 5
+    run = -(-chunks // P)
+    for contiguous in (True, False):
+        tot = 0
+        for p in range(P):
+            ids = range(p * run, min(chunks, (p + 1) * run)) if contiguous else range(p, chunks, P)
+            sub = np.concatenate([m.indices[c * N:(c + 1) * N] for c in ids]) if len(ids) else np.zeros(0, np.uint32)
+            tot += vro.parallel_cache_hits(sub, V, 1, N, 64)
+        assert vro.parallel_cache_hits(m.indices, V, P, N, 64, contiguous) == tot
+    assert vro.parallel_cache_hits(np.array([0, 9], np.uint32), 5, 1, 1, 4) == -1   # index out of range
