@@ -111,6 +111,11 @@ STRATS = [
     ("dyn_phash_128_128", vro.DYN_PHASH, 128, 128),
     ("dyn_ballot_85_64", vro.DYN_BALLOT, 85, 64),
     ("dyn_ballot_200_150", vro.DYN_BALLOT, 200, 150),
+    # the largest configurations each strategy accepts
+    ("static_hash_256", vro.STATIC_HASH, 256, 0),
+    ("dyn_sort_512_512", vro.DYN_SORT, 512, 512),
+    ("dyn_phash_512_512", vro.DYN_PHASH, 512, 512),
+    ("dyn_ballot_512_64", vro.DYN_BALLOT, 512, 64),
 ]
 
 
