@@ -264,6 +264,131 @@ int64_t vro_parallel_cache_hits(const uint32_t *idx, uint64_t n, uint32_t V, uin
     return hits;
 }
 
+/* ------------------------------------------------------------------------
+ * Parallel random walk (Section 5).  An agent's reuse "index" is its packed
+ * cell key x | y << 16; agents on the same cell see the same move
+ * likelihoods, so a batch evaluates each distinct cell once.
+ * ---------------------------------------------------------------------- */
+#define VRO_WALK_KEEP 8
+
+/* The VRO_WALK_KEEP most likely moves from cell (x, y): likelihood =
+ * activity(target) * weight(move) in FP32, moves leaving the grid skipped,
+ * kept in decreasing likelihood with ties to the lower move index.  Returns
+ * how many were kept. */
+static uint32_t walk_top(uint32_t x, uint32_t y, const float *act, uint32_t G, const int8_t *mv, const float *w,
+                         uint32_t M, float *L, uint32_t *mi)
+{
+    uint32_t k = 0;
+    for (uint32_t m = 0; m < M; ++m) {
+        const int64_t tx = (int64_t)x + mv[2 * m], ty = (int64_t)y + mv[2 * m + 1];
+        if (tx < 0 || ty < 0 || tx >= (int64_t)G || ty >= (int64_t)G) continue;
+        const float l = act[(uint64_t)ty * G + (uint64_t)tx] * w[m];
+        uint32_t j = k;                      /* insertion point: after every entry >= l */
+        while (j > 0 && l > L[j - 1]) --j;
+        if (j >= VRO_WALK_KEEP) continue;
+        for (uint32_t t = (k < VRO_WALK_KEEP ? k : VRO_WALK_KEEP - 1); t > j; --t) { L[t] = L[t - 1]; mi[t] = mi[t - 1]; }
+        L[j] = l;
+        mi[j] = m;
+        if (k < VRO_WALK_KEEP) ++k;
+    }
+    return k;
+}
+
+/* One agent's move: target u * S with S the FP32 sum of the kept
+ * likelihoods in order; the first option whose running sum exceeds the
+ * target is taken (the last one if rounding leaves none); an agent whose
+ * options sum to zero stays. */
+static uint32_t walk_choose(uint32_t key, float u, const float *L, const uint32_t *mi, uint32_t k, const int8_t *mv)
+{
+    float S = 0.0f;
+    for (uint32_t j = 0; j < k; ++j) S += L[j];
+    if (k == 0 || !(S > 0.0f)) return key;
+    const float t = u * S;
+    uint32_t pick = k - 1;
+    float run = 0.0f;
+    for (uint32_t j = 0; j < k; ++j) {
+        run += L[j];
+        if (run > t) { pick = j; break; }
+    }
+    const uint32_t x = (key & 0xFFFFu) + (uint32_t)(int32_t)mv[2 * mi[pick]];
+    const uint32_t y = (key >> 16) + (uint32_t)(int32_t)mv[2 * mi[pick] + 1];
+    return (x & 0xFFFFu) | (y << 16);
+}
+
+uint32_t vro_walk_options(uint32_t x, uint32_t y, const float *activity, uint32_t grid, const int8_t *moves,
+                          const float *weights, uint32_t num_moves, float *L, uint32_t *move_index)
+{
+    return walk_top(x, y, activity, grid, moves, weights, num_moves, L, move_index);
+}
+
+uint32_t vro_walk_choose(uint32_t key, float u, const float *L, const uint32_t *move_index, uint32_t k,
+                         const int8_t *moves)
+{
+    return walk_choose(key, u, L, move_index, k, moves);
+}
+
+int vro_walk_step(const uint32_t *keys_in, uint32_t n, const float *activity, uint32_t grid, const int8_t *moves,
+                  const float *weights, uint32_t num_moves, const float *uniforms, int strategy, uint32_t batch,
+                  uint32_t *keys_out, uint64_t *counters)
+{
+    if (counters) memset(counters, 0, 4 * sizeof(uint64_t));
+    if (grid == 0 || grid > 32768 || num_moves == 0 || num_moves > 65535) return VRO_ERR_ARG;
+    if (strategy != VRO_NAIVE && strategy != VRO_STATIC_SORT && strategy != VRO_STATIC_HASH) return VRO_ERR_ARG;
+    if (strategy != VRO_NAIVE && (batch == 0 || batch > 512)) return VRO_ERR_ARG;
+    if (n && (!keys_in || !keys_out || !uniforms || !activity || !moves || !weights)) return VRO_ERR_ARG;
+    for (uint32_t a = 0; a < n; ++a)
+        if ((keys_in[a] & 0xFFFFu) >= grid || (keys_in[a] >> 16) >= grid) {
+            if (counters) counters[3] = VRO_ERR_INDEX_RANGE;
+            return VRO_ERR_INDEX_RANGE;
+        }
+    float L[VRO_WALK_KEEP];
+    uint32_t mi[VRO_WALK_KEEP];
+    uint64_t inv = 0, units = 0;
+    if (strategy == VRO_NAIVE) {
+        for (uint32_t a = 0; a < n; ++a) {
+            const uint32_t k = walk_top(keys_in[a] & 0xFFFFu, keys_in[a] >> 16, activity, grid, moves, weights,
+                                        num_moves, L, mi);
+            keys_out[a] = walk_choose(keys_in[a], uniforms[a], L, mi, k, moves);
+        }
+        inv = units = n;
+    } else {
+        /* per batch: each distinct cell once (first occurrence order) */
+        uint32_t *slot = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)grid * grid);
+        float *bL = (float *)malloc(sizeof(float) * VRO_WALK_KEEP * batch);
+        uint32_t *bm = (uint32_t *)malloc(sizeof(uint32_t) * VRO_WALK_KEEP * batch);
+        uint32_t *bk = (uint32_t *)malloc(sizeof(uint32_t) * batch);
+        uint32_t *cell = (uint32_t *)malloc(sizeof(uint32_t) * batch);
+        if (!slot || !bL || !bm || !bk || !cell) {
+            free(slot); free(bL); free(bm); free(bk); free(cell);
+            return VRO_ERR_ARG;
+        }
+        for (size_t c = 0; c < (size_t)grid * grid; ++c) slot[c] = UINT32_MAX;
+        for (uint32_t a0 = 0; a0 < n; a0 += batch) {
+            const uint32_t a1 = n - a0 < batch ? n : a0 + batch;
+            uint32_t d = 0;
+            for (uint32_t a = a0; a < a1; ++a) {
+                const uint32_t c = (keys_in[a] >> 16) * grid + (keys_in[a] & 0xFFFFu);
+                if (slot[c] == UINT32_MAX) {
+                    slot[c] = d;
+                    cell[d] = c;
+                    bk[d] = walk_top(keys_in[a] & 0xFFFFu, keys_in[a] >> 16, activity, grid, moves, weights,
+                                     num_moves, bL + VRO_WALK_KEEP * d, bm + VRO_WALK_KEEP * d);
+                    ++d;
+                }
+                const uint32_t s = slot[c];
+                keys_out[a] = walk_choose(keys_in[a], uniforms[a], bL + VRO_WALK_KEEP * s, bm + VRO_WALK_KEEP * s,
+                                          bk[s], moves);
+            }
+            for (uint32_t j = 0; j < d; ++j) slot[cell[j]] = UINT32_MAX;
+            inv += d;
+            ++units;
+        }
+        free(slot); free(bL); free(bm); free(bk); free(cell);
+    }
+    if (counters) { counters[0] = inv; counters[1] = units; }
+    return VRO_OK;
+}
+
 /* Stamp set over vertex ids: membership test in O(1) without clearing. */
 typedef struct {
     uint32_t *stamp;

@@ -122,6 +122,27 @@ int64_t vro_fifo_misses(const uint32_t *indices, uint64_t n, uint32_t num_vertic
  * processors in consecutive runs (contiguous != 0) or round robin; lookups
  * see the cache as it stood after the processor's previous cycle (no hit
  * among concurrently shaded duplicates).  -1 on a bad index. */
+/* Section 5, parallel random walk: one step of n agents on a grid x grid
+ * domain.  keys are packed cells x | y << 16; activity is float32[grid *
+ * grid] (cell (x, y) at y * grid + x); moves are int8 (dx, dy) pairs with
+ * float32 weights; uniforms are the agents' random numbers in [0, 1).  A
+ * cell's options are its 8 most likely moves (activity of the target times
+ * the move's weight, moves leaving the grid skipped, ties to the lower move
+ * index); an agent takes the first option whose running FP32 sum exceeds
+ * u * (sum of the options), and stays when they sum to zero.  NAIVE
+ * evaluates every agent's cell; STATIC_SORT / STATIC_HASH evaluate each
+ * distinct cell of a batch of `batch` agents (<= 512) once.  counters =
+ * {cell evaluations, units, 0, status}. */
+/* The pieces of a step, for the tests: a cell's options (count returned,
+ * likelihoods and move indices in order) and one agent's choice. */
+uint32_t vro_walk_options(uint32_t x, uint32_t y, const float *activity, uint32_t grid, const int8_t *moves,
+                          const float *weights, uint32_t num_moves, float *L, uint32_t *move_index);
+uint32_t vro_walk_choose(uint32_t key, float u, const float *L, const uint32_t *move_index, uint32_t k,
+                         const int8_t *moves);
+int vro_walk_step(const uint32_t *keys_in, uint32_t n, const float *activity, uint32_t grid, const int8_t *moves,
+                  const float *weights, uint32_t num_moves, const float *uniforms, int strategy, uint32_t batch,
+                  uint32_t *keys_out, uint64_t *counters);
+
 int64_t vro_parallel_cache_hits(const uint32_t *indices, uint64_t n, uint32_t num_vertices, uint32_t procs,
                                 uint32_t per_cycle, uint32_t entries, int contiguous);
 

@@ -72,6 +72,12 @@ def lib():
         L.vro_fifo_misses.restype = C.c_int64
         L.vro_parallel_cache_hits.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int]
         L.vro_parallel_cache_hits.restype = C.c_int64
+        L.vro_walk_step.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, C.c_uint32, P, C.c_int, C.c_uint32, P, P]
+        L.vro_walk_step.restype = C.c_int
+        L.vro_walk_options.argtypes = [C.c_uint32, C.c_uint32, P, C.c_uint32, P, P, C.c_uint32, P, P]
+        L.vro_walk_options.restype = C.c_uint32
+        L.vro_walk_choose.argtypes = [C.c_uint32, C.c_float, P, P, C.c_uint32, P]
+        L.vro_walk_choose.restype = C.c_uint32
         _lib = L
     return _lib
 
@@ -176,6 +182,38 @@ def parallel_cache_hits(indices, num_vertices, procs, per_cycle, entries, contig
     indices = np.ascontiguousarray(indices, dtype=np.uint32)
     return int(lib().vro_parallel_cache_hits(_ptr(indices), len(indices), num_vertices, procs, per_cycle, entries,
                                              1 if contiguous else 0))
+
+
+def walk_step(keys, setup, uniforms, strategy, batch=0):
+    """One random-walk step (Section 5); returns (status, new keys, counters)."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint32)
+    out = np.zeros_like(keys)
+    cnt = np.zeros(4, dtype=np.uint64)
+    act = np.ascontiguousarray(setup.activity, dtype=np.float32)
+    mv = np.ascontiguousarray(setup.moves, dtype=np.int8)
+    w = np.ascontiguousarray(setup.weights, dtype=np.float32)
+    u = np.ascontiguousarray(uniforms, dtype=np.float32)
+    rc = lib().vro_walk_step(_ptr(keys), len(keys), _ptr(act), setup.grid, _ptr(mv), _ptr(w), len(w), _ptr(u),
+                             strategy, batch, _ptr(out), _ptr(cnt))
+    return rc, out, cnt
+
+
+def walk_options(x, y, setup):
+    """A cell's kept options: (likelihoods float32[k], move indices[k])."""
+    L = np.zeros(8, np.float32)
+    mi = np.zeros(8, np.uint32)
+    act = np.ascontiguousarray(setup.activity, dtype=np.float32)
+    mv = np.ascontiguousarray(setup.moves, dtype=np.int8)
+    w = np.ascontiguousarray(setup.weights, dtype=np.float32)
+    k = lib().vro_walk_options(x, y, _ptr(act), setup.grid, _ptr(mv), _ptr(w), len(w), _ptr(L), _ptr(mi))
+    return L[:k], mi[:k]
+
+
+def walk_choose(key, u, L, mi, moves):
+    L = np.ascontiguousarray(L, dtype=np.float32)
+    mi = np.ascontiguousarray(mi, dtype=np.uint32)
+    mv = np.ascontiguousarray(moves, dtype=np.int8)
+    return int(lib().vro_walk_choose(key, float(u), _ptr(L), _ptr(mi), len(L), _ptr(mv)))
 
 
 def fifo_misses(indices, num_vertices, k):

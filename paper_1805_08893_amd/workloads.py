@@ -465,3 +465,55 @@ def serving_trace(pool, seed: int = 13, n: int = 2000, rate: float = 500.0, ligh
     size = np.array([pool[m][2] for m in mesh], dtype=np.int64)
     nl = rng.integers(lights[0], lights[1] + 1, n)
     return {"arrival": arrival, "size": size, "mesh": mesh, "lights": nl}
+
+
+# --------------------------------------------------------------------------
+# Random walk on a grid (Section 5, parallel random walk)
+# --------------------------------------------------------------------------
+class WalkSetup:
+    """Inputs of the random-walk workload: an activity field over a G x G
+    grid (float32, row-major, cell (x, y) at y * G + x), the move table
+    (every offset within `radius`, scan order by dy then dx, with its
+    step-length weight, float32) and the agents' packed cell keys
+    (x | y << 16)."""
+
+    def __init__(self, grid, activity, moves, weights, keys, seed):
+        self.grid, self.activity, self.moves, self.weights, self.keys, self.seed = \
+            grid, activity, moves, weights, keys, seed
+
+
+def walk_setup(seed: int = 21, grid: int = 256, agents: int = 300_000, radius: int = 16,
+               gaussians: int = 8, beta: float = 1.5, order: str = "hilbert") -> WalkSetup:
+    """Activity = a floor of 1e-3 plus `gaussians` Gaussian bumps (centres
+    uniform on the grid, sigma in [6, 24) cells, weight in [0.5, 1.5)),
+    evaluated in float64 and stored as float32.  Moves: all (dx, dy) with
+    1 <= dx^2 + dy^2 <= radius^2; the weight of a move of length d is
+    d^-(1 + beta), a Levy-flight step-length law, rounded to float32.
+    Agents start on uniformly drawn cells and are stored in the Hilbert
+    order of those cells ("hilbert") or in the order drawn ("random")."""
+    u = uniform(seed, 1, 4 * gaussians).reshape(gaussians, 4)
+    cx, cy = u[:, 0] * grid, u[:, 1] * grid
+    sig, w = 6.0 + 18.0 * u[:, 2], 0.5 + u[:, 3]
+    y, x = np.mgrid[0:grid, 0:grid].astype(np.float64)
+    act = np.full((grid, grid), 1e-3)
+    for g in range(gaussians):
+        act += w[g] * np.exp(-((x - cx[g]) ** 2 + (y - cy[g]) ** 2) / (2.0 * sig[g] ** 2))
+    moves = [(dx, dy) for dy in range(-radius, radius + 1) for dx in range(-radius, radius + 1)
+             if 1 <= dx * dx + dy * dy <= radius * radius]
+    mv = np.array(moves, dtype=np.int8)
+    d = np.sqrt((mv.astype(np.float64) ** 2).sum(1))
+    weights = (d ** -(1.0 + beta)).astype(np.float32)
+    r = u64_stream(seed, 2, 2 * agents)
+    ax = (r[0::2] % np.uint64(grid)).astype(np.uint32)
+    ay = (r[1::2] % np.uint64(grid)).astype(np.uint32)
+    if order == "hilbert":   # agents stored in the Hilbert order of their starting cells
+        bits = max(1, int(np.ceil(np.log2(grid))))
+        perm = np.argsort(hilbert2d(ax.astype(np.uint64), ay.astype(np.uint64), bits), kind="stable")
+        ax, ay = ax[perm], ay[perm]
+    return WalkSetup(grid, act.astype(np.float32).ravel(), mv, weights, ax | (ay << np.uint32(16)), seed)
+
+
+def walk_uniforms(seed: int, step: int, agents: int) -> np.ndarray:
+    """Each agent's random number for one step: 24-bit uniforms in [0, 1),
+    exact in float32."""
+    return uniform(seed, 1000 + step, agents).astype(np.float32)

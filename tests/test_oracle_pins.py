@@ -528,3 +528,80 @@ def test_parallel_cache_concurrency_and_assignment():
             tot += vro.parallel_cache_hits(sub, V, 1, N, 64)
         assert vro.parallel_cache_hits(m.indices, V, P, N, 64, contiguous) == tot
     assert vro.parallel_cache_hits(np.array([0, 9], np.uint32), 5, 1, 1, 4) == -1   # index out of range
+
+
+# ------------------------------------------------- random walk (Section 5)
+def _small_walk(seed=5, grid=24, agents=3000, radius=5):
+    return W.walk_setup(seed, grid=grid, agents=agents, radius=radius, gaussians=3)
+
+
+def test_walk_options_are_the_top8_by_brute_force():
+    """A cell's options equal a full sort of every in-grid move by
+    (likelihood descending, move index ascending), likelihood being one FP32
+    product, including corner and edge cells with few moves."""
+    s = _small_walk()
+    G, mv = s.grid, s.moves.astype(np.int64)
+    A = s.activity.reshape(G, G)
+    for (x, y) in [(0, 0), (G - 1, G - 1), (0, 11), (7, 13), (G - 1, 0), (12, 12)]:
+        tx, ty = x + mv[:, 0], y + mv[:, 1]
+        ok = (tx >= 0) & (ty >= 0) & (tx < G) & (ty < G)
+        m = np.nonzero(ok)[0]
+        l = A[ty[m], tx[m]] * s.weights[m]                    # float32 x float32
+        order = np.lexsort((m, -l.astype(np.float64)))[:8]
+        L, mi = vro.walk_options(x, y, s)
+        np.testing.assert_array_equal(mi, m[order])
+        np.testing.assert_array_equal(L.view(np.uint32), l[order].view(np.uint32))
+    # a flat field: ties everywhere, so the 8 lowest-indexed moves of the
+    # largest weight (the four unit steps, then the four diagonals) win
+    flat = _small_walk()
+    flat.activity = np.ones_like(flat.activity)
+    L, mi = vro.walk_options(10, 10, flat)
+    d2 = (flat.moves.astype(np.int64) ** 2).sum(1)
+    assert sorted(d2[mi].tolist()) == [1, 1, 1, 1, 2, 2, 2, 2]
+    assert mi[:4].tolist() == sorted(mi[:4].tolist())
+
+
+def test_walk_choice_follows_the_running_sum():
+    s = _small_walk()
+    L, mi = vro.walk_options(9, 4, s)
+    cum = np.cumsum(L, dtype=np.float32)                        # sequential FP32 sums
+    key = 9 | (4 << 16)
+    for u in (0.0, 1e-7, 0.25, 0.5, 0.75, 0.999999):
+        t = np.float32(u) * cum[-1]
+        j = int(np.argmax(cum > t)) if (cum > t).any() else len(L) - 1
+        dx, dy = (int(v) for v in s.moves[mi[j]])
+        assert vro.walk_choose(key, u, L, mi, s.moves) == (9 + dx) | ((4 + dy) << 16), u
+    assert vro.walk_choose(key, 0.3, np.zeros(8, np.float32), mi, s.moves) == key      # nothing to weigh: stay
+
+
+def test_walk_step_batching_changes_only_the_counts():
+    """Every strategy moves every agent to the same cell; NAIVE evaluates one
+    cell per agent, the batched ones one per distinct cell of each batch."""
+    s = _small_walk()
+    keys = s.keys
+    for step in range(3):
+        u = W.walk_uniforms(s.seed, step, len(keys))
+        rc, ref, c = vro.walk_step(keys, s, u, vro.NAIVE)
+        assert rc == vro.OK and c[:2].tolist() == [len(keys), len(keys)]
+        for strat in (vro.STATIC_SORT, vro.STATIC_HASH):
+            for b in (1, 7, 256, 512):
+                rc, got, c = vro.walk_step(keys, s, u, strat, b)
+                assert rc == vro.OK
+                np.testing.assert_array_equal(got, ref)
+                d = sum(len(np.unique(keys[i:i + b])) for i in range(0, len(keys), b))
+                assert c[:2].tolist() == [d, -(-len(keys) // b)]
+        # every move stays in the grid
+        assert ((ref & 0xFFFF) < s.grid).all() and ((ref >> 16) < s.grid).all()
+        keys = ref
+
+
+def test_walk_argument_rules():
+    s = _small_walk(agents=10)
+    u = np.zeros(10, np.float32)
+    bad = s.keys.copy()
+    bad[3] = s.grid                                             # x out of range
+    assert vro.walk_step(bad, s, u, vro.STATIC_HASH, 8)[0] == vro.ERR_INDEX_RANGE
+    assert vro.walk_step(s.keys, s, u, vro.STATIC_HASH, 513)[0] == vro.ERR_ARG
+    assert vro.walk_step(s.keys, s, u, vro.DYN_HASH, 64)[0] == vro.ERR_ARG
+    rc, out, c = vro.walk_step(s.keys[:0], s, u[:0], vro.STATIC_HASH, 8)
+    assert rc == vro.OK and c.tolist() == [0, 0, 0, 0]
