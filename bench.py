@@ -317,6 +317,50 @@ def heavy_orders(stage, reps=10):
     return {"workload": "grid2048_offset64", "triangles": 2 * 2047 * 2047, "orders": out}
 
 
+def walk_benchmark(stage, steps=10, batch=512):
+    """The parallel random walk (300,000 agents on 256 x 256, moves within
+    16 cells, 8 options kept): 10 steps searching every agent's cell, and 10
+    searching each distinct cell of 512-agent batches once; both must end
+    with the same agents' cells."""
+    import torch
+    from paper_1805_08893_amd import vr
+    from paper_1805_08893_amd import workloads as W
+    s = W.walk_setup()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a.view(np.int32) if a.dtype == np.uint32 else a)).cuda()
+    act, mv, w = dev(s.activity), dev(s.moves), dev(s.weights)
+    us = [dev(W.walk_uniforms(s.seed, k, len(s.keys))) for k in range(steps)]
+    out, final = {}, {}
+    for name, strat, b in (("naive", vr.VR_NAIVE, 0), (f"hash_{batch}", vr.VR_STATIC_HASH, batch)):
+        keys = dev(s.keys)
+        nxt = torch.empty_like(keys)
+        cnt = torch.zeros((steps, 4), dtype=torch.int64, device="cuda")
+        for k in range(2):   # warm-up
+            stage.check(vr.vr_walk_step(stage.ctx, keys, act, s.grid, mv, w, us[k], strat, b, nxt))
+        torch.cuda.synchronize()
+        keys = dev(s.keys)
+        vr.vr_set_kernel_timing(stage.ctx, True)
+        vr.vr_kernel_times(stage.ctx)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(steps):
+            stage.check(vr.vr_walk_step(stage.ctx, keys, act, s.grid, mv, w, us[k], strat, b, nxt, cnt[k]))
+            keys, nxt = nxt, keys
+        e1.record()
+        torch.cuda.synchronize()
+        kms = np.array(vr.vr_kernel_times(stage.ctx), dtype=np.float64)
+        vr.vr_set_kernel_timing(stage.ctx, False)
+        stage.check(stage.sync()[0])
+        ev = cnt[:, 0].cpu().numpy()
+        out[name] = {"ms_per_step": e0.elapsed_time(e1) / steps, "kernel_ms_per_step": float(kms.mean()),
+                     "searches_per_step": ev.tolist(), "reuse_per_step": (1.0 - ev / len(s.keys)).round(4).tolist()}
+        final[name] = keys.cpu().numpy()
+    names = list(out)
+    out["same_final_cells"] = bool(np.array_equal(final[names[0]], final[names[1]]))
+    out["speedup"] = out["naive"]["ms_per_step"] / out[names[1]]["ms_per_step"]
+    out.update(agents=len(s.keys), grid=s.grid, moves=int(len(s.weights)), steps=steps)
+    return out
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -609,6 +653,13 @@ def main():
             heavy = heavy_orders(stage)
         except Exception as exc:   # the headline line must still be printed
             heavy = {"error": repr(exc)}
+    walk = None
+    if not args.only and not args.no_extra:
+        try:
+            walk = walk_benchmark(stage)
+            progress("random walk done")
+        except Exception as exc:   # the headline line must still be printed
+            walk = {"error": repr(exc)}
     scene = None
     if not args.no_scene and not args.only:
         try:
@@ -630,7 +681,7 @@ def main():
                        "unique_vertices": U, "strategies": [s[0] for s in strategies],
                        "static_batch_tris": 64, "dynamic_max_unique": NU, "dynamic_max_tris": NP,
                        "output": "per-corner shaded vertices + invocation counters"},
-            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "multi": multi, "cold": cold, "plain": plain, "heavy": heavy, "scene": scene,
+            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "multi": multi, "cold": cold, "plain": plain, "heavy": heavy, "walk": walk, "scene": scene,
             "serving": serving}
     print(json.dumps(line), flush=True)
     stage.close()

@@ -204,6 +204,28 @@ vr_status vr_process_draw(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_i
                           const vr_shader_params *shader, vr_strategy strategy,
                           uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out);
 
+/*
+ * Parallel random walk (Section 5): one step of num_agents agents on a
+ * grid x grid domain, reusing the per-cell move search among agents on the
+ * same cell.  d_keys_in / d_keys_out: uint32[num_agents] packed cells
+ * x | y << 16 (may be the same buffer); d_activity: float32[grid * grid],
+ * cell (x, y) at y * grid + x; d_moves: int8[2 * num_moves] (dx, dy);
+ * d_weights: float32[num_moves]; d_uniforms: float32[num_agents] in [0, 1).
+ * A cell's options are its 8 most likely moves (likelihood = activity of the
+ * target times the move's weight in FP32, moves leaving the grid skipped,
+ * ties to the lower move index); an agent takes the first option whose
+ * running FP32 sum exceeds u * (sum of the options) and stays when they sum
+ * to zero.  NAIVE searches every agent's cell; STATIC_HASH searches each
+ * distinct cell of every batch of batch_agents (1..512) agents once.
+ * d_counters: uint64[4] {cell searches, units, 0, 0} or NULL.  A key outside
+ * the grid leaves its agent in place and is reported by the next vr_sync()
+ * as VR_ERR_INDEX_RANGE.  grid <= 32768, num_moves <= 65535.
+ */
+vr_status vr_walk_step(vr_ctx *ctx, const uint32_t *d_keys_in, uint32_t num_agents, const float *d_activity,
+                       uint32_t grid, const int8_t *d_moves, const float *d_weights, uint32_t num_moves,
+                       const float *d_uniforms, vr_strategy strategy, uint32_t batch_agents, uint32_t *d_keys_out,
+                       uint64_t *d_counters);
+
 /* Wait for the context's stream.  Returns the first device-side error raised
  * since the previous vr_sync (then clears it) and, when h_invocations is not
  * NULL, the vertex-shader invocations of all draws since then. */

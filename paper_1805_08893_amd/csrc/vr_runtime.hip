@@ -22,6 +22,7 @@
 #include "vr_plan.h"
 #include "vr_frame.h"
 #include "vr_sched.h"
+#include "vr_walk.h"
 
 using namespace vr;
 
@@ -707,6 +708,60 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
     const uint32_t fin = (uint32_t)std::min<uint64_t>(64, std::max<uint64_t>(1, (nb_bound + 2047) / 2048));
     hipLaunchKernelGGL(k_finish, dim3(fin), dim3(256), 0, c->stream, A.plan, A.num_batches, A.status_cap,
                        (const unsigned long long *)A.agg, A.status, A.counters, A.total_inv);
+    VR_HIP(c, hipGetLastError());
+    return VR_OK;
+}
+
+vr_status vr_walk_step(vr_ctx *c, const uint32_t *d_keys_in, uint32_t num_agents, const float *d_activity,
+                       uint32_t grid, const int8_t *d_moves, const float *d_weights, uint32_t num_moves,
+                       const float *d_uniforms, vr_strategy strategy, uint32_t batch_agents, uint32_t *d_keys_out,
+                       uint64_t *d_counters) {
+    if (!c) return VR_ERR_ARG;
+    if (grid == 0 || grid > 32768) return fail(c, VR_ERR_ARG, "grid %u outside 1..32768", grid);
+    if (num_moves == 0 || num_moves > 65535) return fail(c, VR_ERR_ARG, "num_moves %u outside 1..65535", num_moves);
+    if (strategy != VR_NAIVE && strategy != VR_STATIC_HASH)
+        return fail(c, VR_ERR_ARG, "a walk step takes NAIVE or STATIC_HASH");
+    if (strategy == VR_STATIC_HASH && (batch_agents == 0 || batch_agents > kWalkMaxBatch))
+        return fail(c, VR_ERR_ARG, "batch_agents %u outside 1..%u", batch_agents, kWalkMaxBatch);
+    if (num_agents && (!d_keys_in || !d_keys_out || !d_activity || !d_moves || !d_weights || !d_uniforms))
+        return fail(c, VR_ERR_ARG, "a walk buffer is NULL");
+    DeviceGuard g(c->device);
+    if (num_agents == 0) {
+        hipLaunchKernelGGL(k_empty_draw, dim3(1), dim3(64), 0, c->stream, (unsigned long long *)d_counters,
+                           (uint32_t *)nullptr);
+        VR_HIP(c, hipGetLastError());
+        return VR_OK;
+    }
+    WalkArgs W{};
+    W.keys_in = d_keys_in;
+    W.keys_out = d_keys_out;
+    W.activity = d_activity;
+    W.moves = d_moves;
+    W.weights = d_weights;
+    W.uniforms = d_uniforms;
+    W.n = num_agents;
+    W.grid = grid;
+    W.num_moves = num_moves;
+    W.batch = batch_agents;
+    W.counters = (unsigned long long *)d_counters;
+    W.total_inv = &c->d_words->total_inv;
+    W.err = &c->d_words->err;
+    if (strategy == VR_NAIVE) {
+        TimedRegion timed(c);
+        hipLaunchKernelGGL(k_walk_naive, dim3((num_agents + 255) / 256), dim3(256), 0, c->stream, W);
+        VR_HIP(c, hipGetLastError());
+        return VR_OK;
+    }
+    const uint32_t nb = (num_agents + batch_agents - 1) / batch_agents;
+    vr_status st = ensure(c, c->agg, 8ull * nb);
+    if (st != VR_OK) return st;
+    W.agg = (unsigned long long *)c->agg.ptr;
+    TimedRegion timed(c);
+    hipLaunchKernelGGL(k_walk_hash<kWalkThreads>, dim3(nb), dim3(kWalkThreads), 0, c->stream, W);
+    timed.done();
+    const uint32_t fin = std::min<uint32_t>(64, std::max<uint32_t>(1, (nb + 2047) / 2048));
+    hipLaunchKernelGGL(k_finish, dim3(fin), dim3(256), 0, c->stream, (const uint32_t *)nullptr, nb, nb,
+                       (const unsigned long long *)W.agg, (unsigned long long *)nullptr, W.counters, W.total_inv);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
 }

@@ -28,7 +28,7 @@ DYNAMIC = (VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH, VR_DYN_BALLOT)
 OUT_FLOATS = 12
 
 EXPORTS = ["vr_create", "vr_destroy", "vr_set_stream", "vr_check_args", "vr_plan_dynamic", "vr_process_draw",
-           "vr_sync", "vr_frame_create", "vr_frame_run", "vr_frame_destroy", "vr_process_draws", "vr_autotune",
+           "vr_sync", "vr_walk_step", "vr_frame_create", "vr_frame_run", "vr_frame_destroy", "vr_process_draws", "vr_autotune",
            "vr_set_kernel_timing", "vr_kernel_times", "vr_last_error", "vr_server_create", "vr_server_add_mesh",
            "vr_server_submit", "vr_server_poll", "vr_server_release", "vr_server_fetch", "vr_server_cancel", "vr_server_stats_get",
            "vr_server_destroy", "vr_server_last_error", "vr_server_simulate"]
@@ -131,6 +131,8 @@ def lib():
         L.vr_process_draw.argtypes = [P, P, C.c_uint64, P, C.c_uint32, C.POINTER(vr_shader_params), C.c_int,
                                       C.c_uint32, C.POINTER(vr_opts), C.POINTER(vr_outputs)]
         L.vr_process_draw.restype = C.c_int
+        L.vr_walk_step.argtypes = [P, P, C.c_uint32, P, C.c_uint32, P, P, C.c_uint32, P, C.c_int, C.c_uint32, P, P]
+        L.vr_walk_step.restype = C.c_int
         L.vr_sync.argtypes = [P, C.POINTER(C.c_uint64)]
         L.vr_sync.restype = C.c_int
         L.vr_frame_create.argtypes = [P, C.POINTER(vr_draw), C.c_uint32, C.POINTER(vr_shader_params), C.c_uint32,
@@ -231,6 +233,14 @@ def vr_check_args(num_indices, num_vertices, shader, strategy, batch_tris, opts=
 def vr_plan_dynamic(ctx, indices, num_vertices, max_unique, max_tris, plan):
     return lib().vr_plan_dynamic(ctx, _ptr(indices), indices.numel(), num_vertices, max_unique, max_tris,
                                  _ptr(plan), plan.numel())
+
+
+def vr_walk_step(ctx, keys_in, activity, grid, moves, weights, uniforms, strategy, batch_agents, keys_out,
+                 counters=None):
+    """One random-walk step (device tensors; moves as int8 (dx, dy) pairs)."""
+    return lib().vr_walk_step(ctx, _ptr(keys_in), keys_in.numel(), _ptr(activity), grid, _ptr(moves), _ptr(weights),
+                              weights.numel(), _ptr(uniforms), strategy, batch_agents, _ptr(keys_out),
+                              None if counters is None else counters.data_ptr())
 
 
 def vr_process_draw(ctx, indices, vertices, shader, strategy, batch_tris, opts=None, outputs=None):
