@@ -389,6 +389,51 @@ int vro_walk_step(const uint32_t *keys_in, uint32_t n, const float *activity, ui
     return VRO_OK;
 }
 
+/* ------------------------------------------------------------------------
+ * Triangle setup, the stage that consumes the geometry stage's output queue
+ * (Section 4.2): each assembled triangle's clip-space corners are divided by
+ * w, mapped to a width x height viewport, and the triangle gets its screen
+ * bounding box (clamped to the viewport) and signed area.  It is visible when
+ * every w > 0, the area is positive (counter-clockwise, front facing) and the
+ * clamped box is not empty.  A triangle with a corner at w <= 0 gets an all
+ * zero record.  FP32, in the order written.
+ * ---------------------------------------------------------------------- */
+uint64_t vro_setup(const float *corners, uint64_t T, uint32_t width, uint32_t height, float *records)
+{
+    const float hw = 0.5f * (float)width, hh = 0.5f * (float)height;
+    uint64_t visible = 0;
+    for (uint64_t t = 0; t < T; ++t) {
+        float *r = records + 8 * t;
+        memset(r, 0, 8 * sizeof(float));
+        float sx[3], sy[3];
+        int front = 1;
+        for (int k = 0; k < 3; ++k) {
+            const float *c = corners + 12 * (3 * t + (uint64_t)k);
+            if (!(c[3] > 0.0f)) front = 0;
+            sx[k] = (c[0] / c[3] + 1.0f) * hw;
+            sy[k] = (c[1] / c[3] + 1.0f) * hh;
+        }
+        if (!front) continue;
+        const float area = (sx[1] - sx[0]) * (sy[2] - sy[0]) - (sx[2] - sx[0]) * (sy[1] - sy[0]);
+        float x0 = fminf(fminf(sx[0], sx[1]), sx[2]), x1 = fmaxf(fmaxf(sx[0], sx[1]), sx[2]);
+        float y0 = fminf(fminf(sy[0], sy[1]), sy[2]), y1 = fmaxf(fmaxf(sy[0], sy[1]), sy[2]);
+        x0 = fmaxf(x0, 0.0f);
+        y0 = fmaxf(y0, 0.0f);
+        x1 = fminf(x1, (float)width);
+        y1 = fminf(y1, (float)height);
+        const int vis = area > 0.0f && x0 < x1 && y0 < y1;
+        r[0] = x0;
+        r[1] = y0;
+        r[2] = x1;
+        r[3] = y1;
+        r[4] = area;
+        const uint32_t flag = vis ? 1u : 0u;
+        memcpy(r + 5, &flag, 4);
+        visible += (uint64_t)vis;
+    }
+    return visible;
+}
+
 /* Stamp set over vertex ids: membership test in O(1) without clearing. */
 typedef struct {
     uint32_t *stamp;

@@ -143,6 +143,11 @@ int vro_walk_step(const uint32_t *keys_in, uint32_t n, const float *activity, ui
                   const float *weights, uint32_t num_moves, const float *uniforms, int strategy, uint32_t batch,
                   uint32_t *keys_out, uint64_t *counters);
 
+/* Triangle setup of T assembled triangles (corners as written by a draw):
+ * records float[T][8] = {xmin, ymin, xmax, ymax, area, flags (uint32: 1 =
+ * visible), 0, 0}; returns the number of visible triangles. */
+uint64_t vro_setup(const float *corners, uint64_t T, uint32_t width, uint32_t height, float *records);
+
 int64_t vro_parallel_cache_hits(const uint32_t *indices, uint64_t n, uint32_t num_vertices, uint32_t procs,
                                 uint32_t per_cycle, uint32_t entries, int contiguous);
 

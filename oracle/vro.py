@@ -74,6 +74,8 @@ def lib():
         L.vro_parallel_cache_hits.restype = C.c_int64
         L.vro_walk_step.argtypes = [P, C.c_uint32, P, C.c_uint32, P, P, C.c_uint32, P, C.c_int, C.c_uint32, P, P]
         L.vro_walk_step.restype = C.c_int
+        L.vro_setup.argtypes = [P, C.c_uint64, C.c_uint32, C.c_uint32, P]
+        L.vro_setup.restype = C.c_uint64
         L.vro_walk_options.argtypes = [C.c_uint32, C.c_uint32, P, C.c_uint32, P, P, C.c_uint32, P, P]
         L.vro_walk_options.restype = C.c_uint32
         L.vro_walk_choose.argtypes = [C.c_uint32, C.c_float, P, P, C.c_uint32, P]
@@ -182,6 +184,16 @@ def parallel_cache_hits(indices, num_vertices, procs, per_cycle, entries, contig
     indices = np.ascontiguousarray(indices, dtype=np.uint32)
     return int(lib().vro_parallel_cache_hits(_ptr(indices), len(indices), num_vertices, procs, per_cycle, entries,
                                              1 if contiguous else 0))
+
+
+def setup(corners, width, height):
+    """Triangle setup of assembled corners [3T, 12]: (records float32[T, 8],
+    visible count); records[:, 5] holds the uint32 flags."""
+    corners = np.ascontiguousarray(corners, dtype=np.float32)
+    T = len(corners) // 3
+    rec = np.zeros((T, 8), np.float32)
+    vis = int(lib().vro_setup(_ptr(corners), T, width, height, _ptr(rec)))
+    return rec, vis
 
 
 def walk_step(keys, setup, uniforms, strategy, batch=0):

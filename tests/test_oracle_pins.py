@@ -605,3 +605,50 @@ def test_walk_argument_rules():
     assert vro.walk_step(s.keys, s, u, vro.DYN_HASH, 64)[0] == vro.ERR_ARG
     rc, out, c = vro.walk_step(s.keys[:0], s, u[:0], vro.STATIC_HASH, 8)
     assert rc == vro.OK and c.tolist() == [0, 0, 0, 0]
+
+
+# ------------------------------------- triangle setup (the queue's consumer)
+def _corners(tris_clip):
+    """[T][3][4] clip positions -> corner rows [3T, 12] (other columns 0)."""
+    c = np.zeros((3 * len(tris_clip), 12), np.float32)
+    c[:, :4] = np.asarray(tris_clip, np.float32).reshape(-1, 4)
+    return c
+
+
+def test_setup_hand_cases():
+    ccw = [[-0.5, -0.5, 0, 1], [0.5, -0.5, 0, 1], [0.0, 0.5, 0, 1]]
+    rec, vis = vro.setup(_corners([ccw]), 100, 100)
+    assert vis == 1
+    assert rec[0, :5].tolist() == [25.0, 25.0, 75.0, 75.0, 2500.0] and rec[0, 5:6].view(np.uint32)[0] == 1
+    rec, vis = vro.setup(_corners([ccw[::-1]]), 100, 100)          # clockwise: back facing
+    assert vis == 0 and rec[0, 4] == -2500.0 and rec[0, 5:6].view(np.uint32)[0] == 0
+    behind = [ccw[0], ccw[1], [0.0, 0.5, 0, -1]]                  # a corner behind the eye
+    rec, vis = vro.setup(_corners([behind]), 100, 100)
+    assert vis == 0 and not rec.any()
+    off = [[2.0, 2.0, 0, 1], [3.0, 2.0, 0, 1], [2.5, 3.0, 0, 1]]    # right of and above the viewport
+    rec, vis = vro.setup(_corners([off]), 100, 100)
+    assert vis == 0 and rec[0, 4] > 0 and rec[0, 0] >= rec[0, 2]
+    half = [[-2.0, -0.5, 0, 1], [0.5, -0.5, 0, 1], [0.0, 0.5, 0, 1]]   # partly left of it: clamped
+    rec, vis = vro.setup(_corners([half]), 100, 100)
+    assert vis == 1 and rec[0, 0] == 0.0
+
+
+def test_setup_invariants():
+    rng = np.random.default_rng(4)
+    tri = rng.uniform(-1.5, 1.5, (500, 3, 4)).astype(np.float32)
+    tri[:, :, 3] = rng.uniform(0.5, 2.0, (500, 3)).astype(np.float32)
+    rec, vis = vro.setup(_corners(tri), 640, 480)
+    # scaling a corner's homogeneous coordinates by 2 divides exactly: same record
+    rec2, vis2 = vro.setup(_corners(tri * np.float32(2.0)), 640, 480)
+    assert vis2 == vis and np.array_equal(rec.view(np.uint32), rec2.view(np.uint32))
+    # the area's sign agrees with a float64 cross product wherever it is not tiny
+    p = tri[:, :, :2].astype(np.float64) / tri[:, :, 3:4]
+    sx, sy = (p[:, :, 0] + 1) * 320, (p[:, :, 1] + 1) * 240
+    a64 = (sx[:, 1] - sx[:, 0]) * (sy[:, 2] - sy[:, 0]) - (sx[:, 2] - sx[:, 0]) * (sy[:, 1] - sy[:, 0])
+    big = np.abs(a64) > 1e-2
+    assert (np.sign(rec[big, 4]) == np.sign(a64[big])).all()
+    np.testing.assert_allclose(rec[big, 4], a64[big], rtol=1e-3, atol=1e-2)
+    # visible = positive area and a non-empty clamped box
+    flags = rec[:, 5].view(np.uint32)
+    want = (rec[:, 4] > 0) & (rec[:, 0] < rec[:, 2]) & (rec[:, 1] < rec[:, 3])
+    assert np.array_equal(flags == 1, want) and vis == int(want.sum())
