@@ -205,6 +205,35 @@ vr_status vr_process_draw(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_i
                           uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out);
 
 /*
+ * Streaming (Sections 4.2 and 5): index chunks are drawn as they arrive with
+ * strategies that need no analysis of the index buffer (NAIVE, STATIC_*),
+ * each into one of `slots` corner buffers of chunk_tris triangles (owned by
+ * the stream), and a consumer on a second HIP stream runs triangle setup on
+ * every finished buffer: the clip-space corners are divided by w and mapped
+ * to a width x height viewport; each triangle gets its bounding box clamped
+ * to the viewport and its signed area, and is visible when every w > 0, the
+ * area is positive (counter-clockwise) and the box is not empty (a corner at
+ * w <= 0 gives an all-zero record).  Records land in d_records (caller-owned,
+ * float[records_cap][8] = {xmin, ymin, xmax, ymax, area, flags, 0, 0}, flags
+ * a uint32 with bit 0 = visible) at the triangle's position in the stream.
+ * A buffer is drawn into again only after the consumer has finished it
+ * (events), so memory stays bounded for any stream length.  Static batches
+ * restart at every chunk.  Errors: VR_ERR_ARG (slots outside 1..8,
+ * chunk_tris outside 1..2^24, a dynamic strategy, a chunk above chunk_tris),
+ * VR_ERR_CAPACITY (records_cap exceeded), draw errors as vr_process_draw.
+ */
+typedef struct vr_stream vr_stream;
+vr_status vr_stream_create(vr_ctx *ctx, uint32_t slots, uint32_t chunk_tris, uint32_t width, uint32_t height,
+                           float *d_records, uint64_t records_cap, vr_stream **stream);
+vr_status vr_stream_push(vr_stream *stream, const uint32_t *d_indices, uint64_t num_indices, const float *d_vertices,
+                         uint32_t num_vertices, const vr_shader_params *shader, vr_strategy strategy,
+                         uint32_t batch_tris);
+/* Waits for both stages; totals since creation: triangles pushed, visible
+ * triangles, vertex-shader invocations. */
+vr_status vr_stream_finish(vr_stream *stream, uint64_t *h_triangles, uint64_t *h_visible, uint64_t *h_invocations);
+void vr_stream_destroy(vr_stream *stream);
+
+/*
  * Parallel random walk (Section 5): one step of num_agents agents on a
  * grid x grid domain, reusing the per-cell move search among agents on the
  * same cell.  d_keys_in / d_keys_out: uint32[num_agents] packed cells

@@ -23,6 +23,7 @@
 #include "vr_frame.h"
 #include "vr_sched.h"
 #include "vr_walk.h"
+#include "vr_stream.h"
 
 using namespace vr;
 
@@ -710,6 +711,151 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
                        (const unsigned long long *)A.agg, A.status, A.counters, A.total_inv);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Streams: chunks drawn into a ring of corner slots, consumed by triangle
+// setup on a second HIP stream; events order each slot's reuse.
+// ---------------------------------------------------------------------------
+struct vr_stream {
+    vr_ctx *c = nullptr;
+    hipStream_t cons = nullptr;
+    uint32_t slots = 0, chunk_tris = 0, width = 0, height = 0;
+    f4 *records = nullptr;
+    uint64_t records_cap = 0;
+    unsigned char *mem = nullptr;
+    size_t slot_bytes = 0;
+    unsigned long long *totals = nullptr;   // {visible, invocations, units, 0}
+    std::vector<hipEvent_t> produced, consumed;
+    std::vector<bool> used;
+    uint64_t pushed = 0, next = 0;
+};
+
+namespace {
+f4 *stream_corners(vr_stream *s, uint32_t k) { return (f4 *)(s->mem + k * s->slot_bytes); }
+unsigned long long *stream_counters(vr_stream *s, uint32_t k) {
+    return (unsigned long long *)(s->mem + k * s->slot_bytes + s->slot_bytes - 256);
+}
+void stream_release(vr_stream *s) {
+    if (s->cons) (void)hipStreamSynchronize(s->cons);
+    for (hipEvent_t e : s->produced) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->consumed) (void)hipEventDestroy(e);
+    if (s->cons) (void)hipStreamDestroy(s->cons);
+    if (s->mem) (void)hipFree(s->mem);
+}
+}  // namespace
+
+vr_status vr_stream_create(vr_ctx *c, uint32_t slots, uint32_t chunk_tris, uint32_t width, uint32_t height,
+                           float *d_records, uint64_t records_cap, vr_stream **out) {
+    if (!c || !out) return VR_ERR_ARG;
+    *out = nullptr;
+    if (slots == 0 || slots > 8) return fail(c, VR_ERR_ARG, "slots %u outside 1..8", slots);
+    if (chunk_tris == 0 || chunk_tris > (1u << 24)) return fail(c, VR_ERR_ARG, "chunk_tris outside 1..2^24");
+    if (width == 0 || height == 0 || width > (1u << 24) || height > (1u << 24))
+        return fail(c, VR_ERR_ARG, "viewport %ux%u outside 1..2^24", width, height);
+    if (records_cap && (!d_records || ((uintptr_t)d_records & 15)))
+        return fail(c, VR_ERR_ARG, "records must be a 16-byte aligned device buffer");
+    DeviceGuard g(c->device);
+    vr_stream *s = new vr_stream;
+    s->c = c;
+    s->slots = slots;
+    s->chunk_tris = chunk_tris;
+    s->width = width;
+    s->height = height;
+    s->records = (f4 *)d_records;
+    s->records_cap = records_cap;
+    s->slot_bytes = ((144ull * chunk_tris + 255) & ~(size_t)255) + 256;   // corners, then the draw's counters
+    vr_status st = VR_OK;
+    if (hipMalloc((void **)&s->mem, s->slot_bytes * slots + 256) != hipSuccess) {
+        s->mem = nullptr;
+        st = fail(c, VR_ERR_OOM, "stream slots: out of memory");
+    } else if (hipStreamCreateWithFlags(&s->cons, hipStreamNonBlocking) != hipSuccess) {
+        s->cons = nullptr;
+        st = fail(c, VR_ERR_DEVICE, "stream: cannot create the consumer stream");
+    }
+    for (uint32_t k = 0; st == VR_OK && k < slots; ++k) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+            if (a) (void)hipEventDestroy(a);
+            st = fail(c, VR_ERR_DEVICE, "stream: cannot create events");
+            break;
+        }
+        s->produced.push_back(a);
+        s->consumed.push_back(b);
+    }
+    if (st == VR_OK) {
+        s->totals = (unsigned long long *)(s->mem + s->slot_bytes * slots);
+        if (hipMemsetAsync(s->totals, 0, 32, s->cons) != hipSuccess) st = fail(c, VR_ERR_DEVICE, "stream: memset");
+    }
+    if (st != VR_OK) {
+        stream_release(s);
+        delete s;
+        return st;
+    }
+    s->used.assign(slots, false);
+    *out = s;
+    return VR_OK;
+}
+
+vr_status vr_stream_push(vr_stream *s, const uint32_t *d_indices, uint64_t num_indices, const float *d_vertices,
+                         uint32_t num_vertices, const vr_shader_params *shader, vr_strategy strategy,
+                         uint32_t batch_tris) {
+    if (!s) return VR_ERR_ARG;
+    vr_ctx *c = s->c;
+    if (strategy != VR_NAIVE && strategy != VR_STATIC_BALLOT && strategy != VR_STATIC_SORT &&
+        strategy != VR_STATIC_HASH)
+        return fail(c, VR_ERR_ARG, "a stream takes NAIVE or STATIC_* (no analysis of the index buffer)");
+    if (num_indices % 3) return fail(c, VR_ERR_ARG, "num_indices is not a multiple of 3");
+    const uint64_t T = num_indices / 3;
+    if (T > s->chunk_tris) return fail(c, VR_ERR_ARG, "chunk of %llu triangles above chunk_tris %u",
+                                       (unsigned long long)T, s->chunk_tris);
+    if (s->pushed + T > s->records_cap)
+        return fail(c, VR_ERR_CAPACITY, "records_cap %llu below %llu triangles", (unsigned long long)s->records_cap,
+                    (unsigned long long)(s->pushed + T));
+    DeviceGuard g(c->device);
+    const uint32_t k = (uint32_t)(s->next % s->slots);
+    if (s->used[k]) VR_HIP(c, hipStreamWaitEvent(c->stream, s->consumed[k], 0));   // the consumer is done with it
+    vr_outputs out{};
+    out.corners = (float *)stream_corners(s, k);
+    out.counters = (uint64_t *)stream_counters(s, k);
+    vr_status st = vr_process_draw(c, d_indices, num_indices, d_vertices, num_vertices, shader, strategy, batch_tris,
+                                   nullptr, &out);
+    if (st != VR_OK) return st;
+    VR_HIP(c, hipEventRecord(s->produced[k], c->stream));
+    VR_HIP(c, hipStreamWaitEvent(s->cons, s->produced[k], 0));
+    if (T)
+        hipLaunchKernelGGL(k_setup, dim3((uint32_t)((T + 255) / 256)), dim3(256), 0, s->cons,
+                           (const f4 *)stream_corners(s, k), (uint32_t)T, s->width, s->height,
+                           s->records + 2 * s->pushed, (const unsigned long long *)stream_counters(s, k), s->totals);
+    VR_HIP(c, hipGetLastError());
+    VR_HIP(c, hipEventRecord(s->consumed[k], s->cons));
+    s->used[k] = true;
+    ++s->next;
+    s->pushed += T;
+    return VR_OK;
+}
+
+vr_status vr_stream_finish(vr_stream *s, uint64_t *h_triangles, uint64_t *h_visible, uint64_t *h_invocations) {
+    if (!s) return VR_ERR_ARG;
+    vr_ctx *c = s->c;
+    DeviceGuard g(c->device);
+    VR_HIP(c, hipStreamSynchronize(c->stream));
+    VR_HIP(c, hipStreamSynchronize(s->cons));
+    unsigned long long t[4] = {0, 0, 0, 0};
+    VR_HIP(c, hipMemcpy(t, s->totals, sizeof t, hipMemcpyDeviceToHost));
+    if (h_triangles) *h_triangles = s->pushed;
+    if (h_visible) *h_visible = t[0];
+    if (h_invocations) *h_invocations = t[1];
+    return VR_OK;
+}
+
+void vr_stream_destroy(vr_stream *s) {
+    if (!s) return;
+    DeviceGuard g(s->c->device);
+    (void)hipStreamSynchronize(s->c->stream);
+    stream_release(s);
+    delete s;
 }
 
 vr_status vr_walk_step(vr_ctx *c, const uint32_t *d_keys_in, uint32_t num_agents, const float *d_activity,

@@ -28,7 +28,8 @@ DYNAMIC = (VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH, VR_DYN_BALLOT)
 OUT_FLOATS = 12
 
 EXPORTS = ["vr_create", "vr_destroy", "vr_set_stream", "vr_check_args", "vr_plan_dynamic", "vr_process_draw",
-           "vr_sync", "vr_walk_step", "vr_frame_create", "vr_frame_run", "vr_frame_destroy", "vr_process_draws", "vr_autotune",
+           "vr_sync", "vr_walk_step", "vr_stream_create", "vr_stream_push", "vr_stream_finish",
+           "vr_stream_destroy", "vr_frame_create", "vr_frame_run", "vr_frame_destroy", "vr_process_draws", "vr_autotune",
            "vr_set_kernel_timing", "vr_kernel_times", "vr_last_error", "vr_server_create", "vr_server_add_mesh",
            "vr_server_submit", "vr_server_poll", "vr_server_release", "vr_server_fetch", "vr_server_cancel", "vr_server_stats_get",
            "vr_server_destroy", "vr_server_last_error", "vr_server_simulate"]
@@ -133,6 +134,16 @@ def lib():
         L.vr_process_draw.restype = C.c_int
         L.vr_walk_step.argtypes = [P, P, C.c_uint32, P, C.c_uint32, P, P, C.c_uint32, P, C.c_int, C.c_uint32, P, P]
         L.vr_walk_step.restype = C.c_int
+        L.vr_stream_create.argtypes = [P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, P, C.c_uint64,
+                                       C.POINTER(C.c_void_p)]
+        L.vr_stream_create.restype = C.c_int
+        L.vr_stream_push.argtypes = [P, P, C.c_uint64, P, C.c_uint32, C.POINTER(vr_shader_params), C.c_int,
+                                     C.c_uint32]
+        L.vr_stream_push.restype = C.c_int
+        L.vr_stream_finish.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.vr_stream_finish.restype = C.c_int
+        L.vr_stream_destroy.argtypes = [P]
+        L.vr_stream_destroy.restype = None
         L.vr_sync.argtypes = [P, C.POINTER(C.c_uint64)]
         L.vr_sync.restype = C.c_int
         L.vr_frame_create.argtypes = [P, C.POINTER(vr_draw), C.c_uint32, C.POINTER(vr_shader_params), C.c_uint32,
@@ -233,6 +244,30 @@ def vr_check_args(num_indices, num_vertices, shader, strategy, batch_tris, opts=
 def vr_plan_dynamic(ctx, indices, num_vertices, max_unique, max_tris, plan):
     return lib().vr_plan_dynamic(ctx, _ptr(indices), indices.numel(), num_vertices, max_unique, max_tris,
                                  _ptr(plan), plan.numel())
+
+
+def vr_stream_create(ctx, slots, chunk_tris, width, height, records):
+    """records: float32 device tensor [capacity, 8]."""
+    h = C.c_void_p()
+    st = lib().vr_stream_create(ctx, slots, chunk_tris, width, height, _ptr(records), records.shape[0], C.byref(h))
+    return st, h
+
+
+def vr_stream_push(stream, indices, vertices, shader, strategy, batch_tris):
+    sh = shader if isinstance(shader, vr_shader_params) else make_shader(shader)
+    V = vertices.shape[0] if vertices.dim() == 2 else vertices.numel() // 8
+    return lib().vr_stream_push(stream, _ptr(indices), indices.numel(), _ptr(vertices), V, C.byref(sh), strategy,
+                                batch_tris)
+
+
+def vr_stream_finish(stream):
+    t, v, i = C.c_uint64(0), C.c_uint64(0), C.c_uint64(0)
+    st = lib().vr_stream_finish(stream, C.byref(t), C.byref(v), C.byref(i))
+    return st, int(t.value), int(v.value), int(i.value)
+
+
+def vr_stream_destroy(stream):
+    lib().vr_stream_destroy(stream)
 
 
 def vr_walk_step(ctx, keys_in, activity, grid, moves, weights, uniforms, strategy, batch_agents, keys_out,
