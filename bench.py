@@ -361,6 +361,38 @@ def walk_benchmark(stage, steps=10, batch=512):
     return out
 
 
+def stream_benchmark(stage, idx, vtx, sp, T, chunk=65536, reps=5):
+    """The bench mesh streamed in 64K-triangle chunks with static ballot
+    rounds (no analysis of the index buffer) through a ring of 1, 2 or 4
+    corner buffers, triangle setup (1920 x 1080) consuming each buffer on a
+    second HIP stream; against the whole mesh as one chunk.  Host wall time
+    from the first push to both stages finished."""
+    import torch
+    from paper_1805_08893_amd import vr
+    rec = torch.empty((T, 8), dtype=torch.float32, device="cuda")
+    sh = vr.make_shader(sp)
+    out = {}
+    for name, slots, ch in (("whole", 1, T), ("ring1", 1, chunk), ("ring2", 2, chunk), ("ring4", 4, chunk)):
+        times, vis = [], 0
+        for _ in range(reps + 1):
+            st, h = vr.vr_stream_create(stage.ctx, slots, ch, 1920, 1080, rec)
+            stage.check(st)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c0 in range(0, T, ch):
+                c1 = min(T, c0 + ch)
+                stage.check(vr.vr_stream_push(h, idx[3 * c0:3 * c1], vtx, sh, vr.VR_STATIC_BALLOT, 64))
+            st, tris, vis, inv = vr.vr_stream_finish(h)
+            times.append(time.perf_counter() - t0)
+            vr.vr_stream_destroy(h)
+            stage.check(st)
+        t = float(np.median(times[1:]))
+        out[name] = {"slots": slots, "chunk_tris": ch, "ms": t * 1e3, "tri_per_s": T / t, "visible": vis,
+                     "invocations": inv}
+    stage.check(stage.sync()[0])
+    return out
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -653,6 +685,13 @@ def main():
             heavy = heavy_orders(stage)
         except Exception as exc:   # the headline line must still be printed
             heavy = {"error": repr(exc)}
+    stream = None
+    if not args.only and not args.no_extra:
+        try:
+            stream = stream_benchmark(stage, idx, vtx, sp, T)
+            progress("streaming done")
+        except Exception as exc:   # the headline line must still be printed
+            stream = {"error": repr(exc)}
     walk = None
     if not args.only and not args.no_extra:
         try:
@@ -681,7 +720,7 @@ def main():
                        "unique_vertices": U, "strategies": [s[0] for s in strategies],
                        "static_batch_tris": 64, "dynamic_max_unique": NU, "dynamic_max_tris": NP,
                        "output": "per-corner shaded vertices + invocation counters"},
-            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "multi": multi, "cold": cold, "plain": plain, "heavy": heavy, "walk": walk, "scene": scene,
+            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "multi": multi, "cold": cold, "plain": plain, "heavy": heavy, "stream": stream, "walk": walk, "scene": scene,
             "serving": serving}
     print(json.dumps(line), flush=True)
     stage.close()
