@@ -218,7 +218,8 @@ vr_status vr_process_draw(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_i
  * a uint32 with bit 0 = visible) at the triangle's position in the stream.
  * A buffer is drawn into again only after the consumer has finished it
  * (events), so memory stays bounded for any stream length.  Static batches
- * restart at every chunk.  Errors: VR_ERR_ARG (slots outside 1..8,
+ * restart at every chunk.  A stream belongs to its context and must be
+ * destroyed before it; push is not thread safe.  Errors: VR_ERR_ARG (slots outside 1..8,
  * chunk_tris outside 1..2^24, a dynamic strategy, a chunk above chunk_tris),
  * VR_ERR_CAPACITY (records_cap exceeded), draw errors as vr_process_draw.
  */

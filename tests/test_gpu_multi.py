@@ -111,6 +111,11 @@ def test_multi_argument_rules(stage):
     d = vr.make_draw(idx, vtx, 0, vr.VR_MULTI, 1, corners)
     st, _ = vr.vr_frame_create(stage.ctx, [d], [sp], capture_graph=False)
     assert st == vr.VR_ERR_ARG
+    from paper_1805_08893_amd.serve import Server
+    with Server(64 << 20) as srv:                        # the server serves streaming strategies only
+        mid = srv.add_mesh(idx, vtx)
+        assert vr.vr_server_submit(srv.h, vr.make_request(mid, m.num_tris, W.shader_for_mesh(m, W.SHADER_MVP, 1),
+                                                          vr.VR_MULTI, 1))[0] == vr.VR_ERR_ARG
     bad = m.indices.copy()
     bad[5] = m.num_verts
     got = stage.alloc_outputs(m.num_tris, vr.VR_MULTI, 1, corners=True)
