@@ -56,15 +56,19 @@ __device__ __forceinline__ void walk_clear(float (&L)[kWalkKeep], uint32_t (&mi)
 // The kWalkKeep most likely moves among moves [m0, m1) from cell (x, y):
 // likelihood = activity of the target times the move's weight (one FP32
 // product), moves leaving the grid skipped, descending with ties to the
-// lower move index.  Returns the number of moves that stay in the grid.
+// lower move index.  The activity is read from `act`, a window of the field
+// with row pitch `pitch` whose first cell is (ox, oy) and which holds every
+// in-grid target (the whole field, or a tile staged in LDS).  Returns the
+// number of moves that stay in the grid.
 __device__ __forceinline__ uint32_t walk_search(const WalkArgs &W, uint32_t x, uint32_t y, uint32_t m0, uint32_t m1,
-                                                float (&L)[kWalkKeep], uint32_t (&mi)[kWalkKeep]) {
+                                                float (&L)[kWalkKeep], uint32_t (&mi)[kWalkKeep], const float *act,
+                                                uint32_t pitch, int32_t ox, int32_t oy) {
     uint32_t valid = 0;
     for (uint32_t m = m0; m < m1; ++m) {
         const int32_t tx = (int32_t)x + W.moves[2 * m], ty = (int32_t)y + W.moves[2 * m + 1];
         if (tx < 0 || ty < 0 || tx >= (int32_t)W.grid || ty >= (int32_t)W.grid) continue;
         ++valid;
-        walk_insert(L, mi, W.activity[(uint32_t)ty * W.grid + (uint32_t)tx] * W.weights[m], m);
+        walk_insert(L, mi, act[(uint32_t)(ty - oy) * pitch + (uint32_t)(tx - ox)] * W.weights[m], m);
     }
     return valid;
 }
@@ -73,7 +77,7 @@ __device__ __forceinline__ uint32_t walk_search(const WalkArgs &W, uint32_t x, u
 __device__ __forceinline__ uint32_t walk_options(const WalkArgs &W, uint32_t x, uint32_t y, float (&L)[kWalkKeep],
                                                  uint32_t (&mi)[kWalkKeep]) {
     walk_clear(L, mi);
-    const uint32_t valid = walk_search(W, x, y, 0, W.num_moves, L, mi);
+    const uint32_t valid = walk_search(W, x, y, 0, W.num_moves, L, mi, W.activity, W.grid, 0, 0);
     return valid < kWalkKeep ? valid : kWalkKeep;
 }
 
@@ -157,21 +161,33 @@ __global__ __launch_bounds__(256) void k_walk_naive(WalkArgs W) {
 // slots); the lane that inserts a cell takes the next id; each distinct cell
 // is evaluated once into LDS; every agent then takes its move from its
 // cell's options.
+// Activity cells a batch can stage in LDS: the bounding box of its distinct
+// cells grown by the longest move, when it holds at most this many cells.
+constexpr uint32_t kWalkTile = 4096;
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_walk_hash(WalkArgs W) {
     constexpr uint32_t S = 2 * kWalkMaxBatch, mask = S - 1;
-    __shared__ uint32_t s_table[S], s_id[S];
+    // s_raw holds the hash table and the slot ids while the batch's cells are
+    // inserted, then the staged activity tile
+    __shared__ uint32_t s_raw[kWalkTile];
+    uint32_t *s_table = s_raw, *s_id = s_raw + S;
+    float *s_tile = (float *)s_raw;
     __shared__ uint32_t s_key[kWalkMaxBatch], s_uniq[kWalkMaxBatch];
     __shared__ uint16_t s_slot[kWalkMaxBatch];
     __shared__ float s_L[kWalkMaxBatch][kWalkKeep];
     __shared__ uint16_t s_mi[kWalkMaxBatch][kWalkKeep];
     __shared__ uint8_t s_k[kWalkMaxBatch];
-    __shared__ uint32_t s_count;
+    __shared__ uint32_t s_count, s_box[5];   // min x, min y, max x, max y, longest move
     const uint32_t tid = threadIdx.x, b = blockIdx.x;
     if (b == 0 && tid < 4 && W.counters) W.counters[tid] = 0;   // k_finish adds to them afterwards
     const uint32_t a0 = b * W.batch, cnt = min(W.batch, W.n - a0);
     for (uint32_t s = tid; s < S; s += NT) s_table[s] = kEmpty;
-    if (tid == 0) s_count = 0;
+    if (tid == 0) {
+        s_count = 0;
+        s_box[0] = s_box[1] = 0xFFFFFFFFu;
+        s_box[2] = s_box[3] = s_box[4] = 0;
+    }
     __syncthreads();
     for (uint32_t i = tid; i < cnt; i += NT) {
         const uint32_t key = W.keys_in[a0 + i];
@@ -190,8 +206,41 @@ __global__ __launch_bounds__(NT) void k_walk_hash(WalkArgs W) {
         }
         s_slot[i] = (uint16_t)p;
     }
+    for (uint32_t m = tid; m < W.num_moves; m += NT) {
+        const int32_t dx = W.moves[2 * m], dy = W.moves[2 * m + 1];
+        atomicMax(&s_box[4], (uint32_t)max(max(dx, -dx), max(dy, -dy)));
+    }
     __syncthreads();
     const uint32_t inv = s_count;
+    for (uint32_t i = tid; i < cnt; i += NT) s_slot[i] = (uint16_t)s_id[s_slot[i]];   // slot -> id
+    for (uint32_t j = tid; j < inv; j += NT) {
+        const uint32_t key = s_uniq[j], x = key & 0xFFFFu, y = key >> 16;
+        if (x < W.grid && y < W.grid) {
+            atomicMin(&s_box[0], x);
+            atomicMin(&s_box[1], y);
+            atomicMax(&s_box[2], x);
+            atomicMax(&s_box[3], y);
+        }
+    }
+    __syncthreads();   // the table and ids are dead from here on
+    // the tile: the cells' bounding box grown by the longest move, clipped
+    const int32_t R = (int32_t)s_box[4];
+    const bool any = s_box[0] <= s_box[2];
+    const int32_t tx0 = any ? max(0, (int32_t)s_box[0] - R) : 0, ty0 = any ? max(0, (int32_t)s_box[1] - R) : 0;
+    const int32_t tx1 = any ? min((int32_t)W.grid - 1, (int32_t)s_box[2] + R) : 0;
+    const int32_t ty1 = any ? min((int32_t)W.grid - 1, (int32_t)s_box[3] + R) : 0;
+    const uint32_t tw = (uint32_t)(tx1 - tx0 + 1), th = (uint32_t)(ty1 - ty0 + 1);
+    const bool tiled = any && tw * th <= kWalkTile;
+    if (tiled) {
+        for (uint32_t c = tid; c < tw * th; c += NT) {
+            const uint32_t r = c / tw;
+            s_tile[c] = W.activity[(uint32_t)(ty0 + (int32_t)r) * W.grid + (uint32_t)tx0 + (c - r * tw)];
+        }
+        __syncthreads();
+    }
+    const float *act = tiled ? (const float *)s_tile : W.activity;
+    const uint32_t pitch = tiled ? tw : W.grid;
+    const int32_t ox = tiled ? tx0 : 0, oy = tiled ? ty0 : 0;
     // four lanes per distinct cell, each searching a quarter of the moves;
     // the quad's lists are merged lane 1 into 0 and 3 into 2, then 2 into 0
     const uint32_t quarter = (W.num_moves + 3) / 4;
@@ -207,7 +256,7 @@ __global__ __launch_bounds__(NT) void k_walk_hash(WalkArgs W) {
         uint32_t valid = 0;
         if (ok)
             valid = walk_search(W, key & 0xFFFFu, key >> 16, min(W.num_moves, q * quarter),
-                                min(W.num_moves, (q + 1) * quarter), L, mi);
+                                min(W.num_moves, (q + 1) * quarter), L, mi, act, pitch, ox, oy);
         walk_merge_xor(L, mi, 1);
         walk_merge_xor(L, mi, 2);
         valid += (uint32_t)__shfl_xor((int)valid, 1, kWave);
@@ -224,7 +273,7 @@ __global__ __launch_bounds__(NT) void k_walk_hash(WalkArgs W) {
     __syncthreads();
     for (uint32_t i = tid; i < cnt; i += NT) {
         const uint32_t key = s_key[i];
-        const uint32_t id = s_id[s_slot[i]];
+        const uint32_t id = s_slot[i];
         float L[kWalkKeep];
         uint32_t mi[kWalkKeep];
 #pragma unroll
