@@ -67,3 +67,20 @@ def test_large_dynamic_hash_general_plan(big):
     print("[large] dynamic hash 256/256", flush=True)
     B = -(-T // 254)
     _check(*big, vr.VR_DYN_HASH, 256, 256, T + 2 * B)
+
+
+def test_large_static_ballot(big):
+    """A 64-triangle strip batch has 66 distinct indices: a round of 62
+    triangles (64 distinct) and one of 2 (4 distinct), 68 invocations."""
+    from paper_1805_08893_amd import vr
+    print("[large] static ballot 64", flush=True)
+    full, rest = divmod(T, 64)
+    tail = 0 if rest == 0 else (rest + 2 if rest <= 62 else 64 + (rest - 62 + 2))
+    _check(*big, vr.VR_STATIC_BALLOT, 64, 0, full * 68 + tail)
+
+
+def test_large_dynamic_sort(big):
+    from paper_1805_08893_amd import vr
+    print("[large] dynamic sort 256/256", flush=True)
+    B = -(-T // 254)
+    _check(*big, vr.VR_DYN_SORT, 256, 256, T + 2 * B)
