@@ -346,6 +346,25 @@ vr_status vr_set_kernel_timing(vr_ctx *ctx, int enable);
 vr_status vr_kernel_times(vr_ctx *ctx, float *ms, uint32_t cap, uint32_t *count);
 
 /*
+ * Self-test of the vertex programs' rounded arithmetic.  The programs need
+ * correctly rounded division and square root (IEEE-754 round to nearest
+ * even); the library computes them with short sequences on the operands
+ * whose intermediates stay normal and with the compiler's full IEEE
+ * sequences on the rest.  This call evaluates the library's version of
+ * `fn` (0 = 1/x, 1 = sqrt(x), 2 = 1/sqrt(x) with both operations rounded)
+ * on the float32 operands whose bit patterns are first .. first + count - 1
+ * and compares each result bit for bit with the compiler's IEEE sequence.
+ * *h_mismatches (host) receives the number of operands that differ; d_out
+ * (device, `count` floats, or NULL) receives the results.  The full range
+ * (first 0, count 2^32) takes a few milliseconds.  Runs on the context's
+ * stream and waits for it.
+ * Errors: VR_ERR_ARG (NULL ctx or h_mismatches, fn > 2, first + count >
+ * 2^32), VR_ERR_OOM, VR_ERR_DEVICE.
+ */
+vr_status vr_math_selftest(vr_ctx *ctx, uint32_t fn, uint64_t first, uint64_t count, float *d_out,
+                           uint64_t *h_mismatches);
+
+/*
  * Request server: continuous batching of draw requests against meshes that
  * stay resident in device memory (the geometry stage of Section 4.2 fed by
  * a stream of requests instead of one draw call).

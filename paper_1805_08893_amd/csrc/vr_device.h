@@ -38,9 +38,67 @@ __device__ __forceinline__ float xrow(const float *M, int r, float x, float y, f
                           __builtin_fmaf(M[4 * r + 1], y, __builtin_fmaf(M[4 * r + 0], x, M[4 * r + 3])));
 }
 
+// Correctly rounded reciprocal and square root.  The compiler's IEEE
+// sequences scale their operands and test for special values; for operands
+// whose intermediates all stay normal that is not needed, and a shorter
+// sequence gives the same bits:
+//  * 1/x for |x| in [2^-125, 2^125]: the hardware reciprocal (within one ulp)
+//    and one Newton-Raphson step on the exact FMA residual 1 - x.y;
+//  * sqrt(x) for x in [2^-96, 2^126]: the hardware square root (within one
+//    ulp), replaced by the neighbour s -/+ 1 ulp that the sign of the FMA
+//    residual x - s'.s selects.
+// Every other operand (zero, denormal, huge, negative, inf, NaN) takes the
+// compiler's sequence.  vr_math_selftest compares both against the
+// compiler's sequences bit for bit over all 2^32 float32 operands
+// (k_math_selftest).
+__device__ __forceinline__ bool recip_fast_ok(float x) {
+    const float ax = __builtin_fabsf(x);
+    return ax >= 0x1p-125f && ax <= 0x1p125f;
+}
+__device__ __forceinline__ float recip_fast(float x) {
+    const float y = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(__builtin_fmaf(-x, y, 1.0f), y, y);
+}
+__device__ __forceinline__ bool sqrt_fast_ok(float x) { return x >= 0x1p-96f && x <= 0x1p126f; }
+__device__ __forceinline__ float sqrt_fast(float x) {
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float lo = __uint_as_float(__float_as_uint(s) - 1u), hi = __uint_as_float(__float_as_uint(s) + 1u);
+    const float r = __builtin_fmaf(-lo, s, x) <= 0.0f ? lo : s;
+    return __builtin_fmaf(-hi, s, x) > 0.0f ? hi : r;
+}
+
+// The fallback runs only when a lane of the wavefront needs it: the branch
+// on the ballot is a scalar one, so the common case pays two compares.
+__device__ __forceinline__ float recip_rn(float x) {
+    float y = recip_fast(x);
+    const bool other = !recip_fast_ok(x);
+    if (__builtin_expect(__ballot(other) != 0, 0)) {
+        if (other) y = 1.0f / x;
+    }
+    return y;
+}
+__device__ __forceinline__ float sqrt_rn(float x) {
+    float r = sqrt_fast(x);
+    const bool other = !sqrt_fast_ok(x);
+    if (__builtin_expect(__ballot(other) != 0, 0)) {
+        if (other) r = __builtin_sqrtf(x);
+    }
+    return r;
+}
+// 1/sqrt(s) with both operations rounded: a square root of the fast range
+// lies in [2^-48, 2^63], inside the reciprocal's, so one test covers both.
+__device__ __forceinline__ float inv_sqrt_rn(float s) {
+    float q = recip_fast(sqrt_fast(s));
+    const bool other = !sqrt_fast_ok(s);
+    if (__builtin_expect(__ballot(other) != 0, 0)) {
+        if (other) q = 1.0f / __builtin_sqrtf(s);
+    }
+    return q;
+}
+
 __device__ __forceinline__ void normalize3(float &x, float &y, float &z) {
     float s = dot3(x, y, z, x, y, z);
-    float q = 1.0f / __builtin_sqrtf(s);
+    float q = inv_sqrt_rn(s);
     x = x * q;
     y = y * q;
     z = z * q;
@@ -84,7 +142,17 @@ __device__ __forceinline__ void shade_vertex(const vr_shader_params &sh, float4 
             const float *L = sh.lights[l];
             const float dx = L[0] - wx, dy = L[1] - wy, dz = L[2] - wz;
             const float d2 = dot3(dx, dy, dz, dx, dy, dz);
-            const float inv = 1.0f / __builtin_sqrtf(d2);
+            const float ad = __builtin_fmaf(sh.katt, d2, 1.0f);
+            // 1/sqrt(d2) and the attenuation 1/(katt.d2 + 1), one range test
+            float inv = recip_fast(sqrt_fast(d2));
+            float att = recip_fast(ad);
+            const bool other = !(sqrt_fast_ok(d2) && recip_fast_ok(ad));
+            if (__builtin_expect(__ballot(other) != 0, 0)) {
+                if (other) {
+                    inv = 1.0f / __builtin_sqrtf(d2);
+                    att = 1.0f / ad;
+                }
+            }
             const float lx = dx * inv, ly = dy * inv, lz = dz * inv;
             const float ndl = dot3(mx, my, mz, lx, ly, lz);
             const float df = ndl > 0.0f ? ndl : 0.0f;
@@ -95,7 +163,6 @@ __device__ __forceinline__ void shade_vertex(const vr_shader_params &sh, float4 
             const float rv = dot3(rx, ry, rz, vx, vy, vz);
             float sp = rv > 0.0f ? rv : 0.0f;
             for (uint32_t s = 0; s < sh.spec_squarings; ++s) sp = sp * sp;
-            const float att = 1.0f / __builtin_fmaf(sh.katt, d2, 1.0f);
             const float k = att * __builtin_fmaf(sh.ks, sp, sh.kd * df);
             cr = __builtin_fmaf(k, L[3], cr);
             cg = __builtin_fmaf(k, L[4], cg);

@@ -24,6 +24,7 @@
 #include "vr_sched.h"
 #include "vr_walk.h"
 #include "vr_stream.h"
+#include "vr_selftest.h"
 
 using namespace vr;
 
@@ -54,6 +55,7 @@ struct vr_ctx {
     std::string error;
     CtxWords *d_words = nullptr;
     Scratch status, agg, plan, plan_work, tune, shaded;   // shaded: MULTI's vertex pass
+    Scratch selftest;                                      // vr_math_selftest's counter
     uint32_t host_err = 0;   // data error found on the host, reported by vr_sync
     uint32_t plan_epoch = 0;  // numbers planning calls (0 is never used)
     bool timing = false;
@@ -1130,6 +1132,31 @@ vr_status vr_kernel_times(vr_ctx *c, float *ms, uint32_t cap, uint32_t *count) {
         VR_HIP(c, hipEventElapsedTime(&ms[i], c->ev_pool[i].first, c->ev_pool[i].second));
     if (count) *count = (uint32_t)n;
     c->ev_used = 0;
+    return VR_OK;
+}
+
+vr_status vr_math_selftest(vr_ctx *c, uint32_t fn, uint64_t first, uint64_t count, float *d_out,
+                           uint64_t *h_mismatches) {
+    if (!c) return VR_ERR_ARG;
+    if (!h_mismatches || fn > 2 || first > (1ull << 32) || count > (1ull << 32) - first)
+        return fail(c, VR_ERR_ARG, "math self-test: bad arguments (fn %u, first %llu, count %llu)", fn,
+                    (unsigned long long)first, (unsigned long long)count);
+    DeviceGuard g(c->device);
+    vr_status st = ensure(c, c->selftest, sizeof(unsigned long long));
+    if (st != VR_OK) return st;
+    auto *d_cnt = (unsigned long long *)c->selftest.ptr;
+    VR_HIP(c, hipMemsetAsync(d_cnt, 0, sizeof *d_cnt, c->stream));
+    const uint64_t per = 1ull << 30;   // operands per launch
+    for (uint64_t done = 0; done < count; done += per) {
+        const uint64_t n = std::min(per, count - done);
+        hipLaunchKernelGGL(k_math_selftest, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, fn,
+                           first + done, n, d_out ? d_out + done : nullptr, d_cnt);
+        VR_HIP(c, hipGetLastError());
+    }
+    unsigned long long h = 0;
+    VR_HIP(c, hipMemcpyAsync(&h, d_cnt, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    VR_HIP(c, hipStreamSynchronize(c->stream));
+    *h_mismatches = h;
     return VR_OK;
 }
 

@@ -30,7 +30,7 @@ OUT_FLOATS = 12
 EXPORTS = ["vr_create", "vr_destroy", "vr_set_stream", "vr_check_args", "vr_plan_dynamic", "vr_process_draw",
            "vr_sync", "vr_walk_step", "vr_stream_create", "vr_stream_push", "vr_stream_finish",
            "vr_stream_destroy", "vr_frame_create", "vr_frame_run", "vr_frame_destroy", "vr_process_draws", "vr_autotune",
-           "vr_set_kernel_timing", "vr_kernel_times", "vr_last_error", "vr_server_create", "vr_server_add_mesh",
+           "vr_set_kernel_timing", "vr_kernel_times", "vr_math_selftest", "vr_last_error", "vr_server_create", "vr_server_add_mesh",
            "vr_server_submit", "vr_server_poll", "vr_server_release", "vr_server_fetch", "vr_server_cancel", "vr_server_stats_get",
            "vr_server_destroy", "vr_server_last_error", "vr_server_simulate"]
 
@@ -159,6 +159,8 @@ def lib():
         L.vr_set_kernel_timing.restype = C.c_int
         L.vr_kernel_times.argtypes = [P, C.POINTER(C.c_float), C.c_uint32, C.POINTER(C.c_uint32)]
         L.vr_kernel_times.restype = C.c_int
+        L.vr_math_selftest.argtypes = [P, C.c_uint32, C.c_uint64, C.c_uint64, P, C.POINTER(C.c_uint64)]
+        L.vr_math_selftest.restype = C.c_int
         L.vr_last_error.argtypes = [P]
         L.vr_last_error.restype = C.c_char_p
         L.vr_server_create.argtypes = [C.c_int, C.POINTER(vr_server_config), C.POINTER(C.c_void_p)]
@@ -342,6 +344,15 @@ def vr_kernel_times(ctx, cap=4096):
     if st != VR_OK:
         raise VrError(st, vr_last_error(ctx))
     return [buf[i] for i in range(min(n.value, cap))]
+
+
+def vr_math_selftest(ctx, fn, first=0, count=1 << 32, out=None):
+    """Rounded-arithmetic self-test (fn 0 = 1/x, 1 = sqrt, 2 = 1/sqrt) over the
+    float32 bit patterns [first, first + count); returns (status, mismatches).
+    `out`, a device tensor of `count` floats, receives the results."""
+    m = C.c_uint64(0)
+    st = lib().vr_math_selftest(ctx, fn, first, count, None if out is None else out.data_ptr(), C.byref(m))
+    return st, int(m.value)
 
 
 # ---------------------------------------------------------------- convenience

@@ -97,3 +97,4 @@ def test_argument_rules_match_oracle(name, case):
 def test_null_context_is_an_argument_error():
     assert vr.lib().vr_sync(None, None) == vr.VR_ERR_ARG
     assert vr.lib().vr_set_stream(None, None) == vr.VR_ERR_ARG
+    assert vr.lib().vr_math_selftest(None, 0, 0, 1, None, None) == vr.VR_ERR_ARG
