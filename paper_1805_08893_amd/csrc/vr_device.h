@@ -51,15 +51,10 @@ __device__ __forceinline__ float xrow(const float *M, int r, float x, float y, f
 // compiler's sequence.  vr_math_selftest compares both against the
 // compiler's sequences bit for bit over all 2^32 float32 operands
 // (k_math_selftest).
-__device__ __forceinline__ bool recip_fast_ok(float x) {
-    const float ax = __builtin_fabsf(x);
-    return ax >= 0x1p-125f && ax <= 0x1p125f;
-}
 __device__ __forceinline__ float recip_fast(float x) {
     const float y = __builtin_amdgcn_rcpf(x);
     return __builtin_fmaf(__builtin_fmaf(-x, y, 1.0f), y, y);
 }
-__device__ __forceinline__ bool sqrt_fast_ok(float x) { return x >= 0x1p-96f && x <= 0x1p126f; }
 __device__ __forceinline__ float sqrt_fast(float x) {
     const float s = __builtin_amdgcn_sqrtf(x);
     const float lo = __uint_as_float(__float_as_uint(s) - 1u), hi = __uint_as_float(__float_as_uint(s) + 1u);
@@ -67,21 +62,27 @@ __device__ __forceinline__ float sqrt_fast(float x) {
     return __builtin_fmaf(-hi, s, x) > 0.0f ? hi : r;
 }
 
-// The fallback runs only when a lane of the wavefront needs it: the branch
-// on the ballot is a scalar one, so the common case pays two compares.
+// Lanes whose operand lies outside [lo, hi] (NaN included), as a wavefront
+// mask: one ballot per compare keeps the test on compare results in scalar
+// registers.  The fallback below runs only when the mask is not empty (a
+// scalar branch), under an execution mask of exactly those lanes.
+__device__ __forceinline__ uint64_t lanes_outside(float x, float lo, float hi) {
+    return __builtin_amdgcn_ballot_w64(!(x >= lo)) | __builtin_amdgcn_ballot_w64(!(x <= hi));
+}
+
 __device__ __forceinline__ float recip_rn(float x) {
     float y = recip_fast(x);
-    const bool other = !recip_fast_ok(x);
-    if (__builtin_expect(__ballot(other) != 0, 0)) {
-        if (other) y = 1.0f / x;
+    const uint64_t other = lanes_outside(__builtin_fabsf(x), 0x1p-125f, 0x1p125f);
+    if (__builtin_expect(other != 0, 0)) {
+        if (__builtin_amdgcn_inverse_ballot_w64(other)) y = 1.0f / x;
     }
     return y;
 }
 __device__ __forceinline__ float sqrt_rn(float x) {
     float r = sqrt_fast(x);
-    const bool other = !sqrt_fast_ok(x);
-    if (__builtin_expect(__ballot(other) != 0, 0)) {
-        if (other) r = __builtin_sqrtf(x);
+    const uint64_t other = lanes_outside(x, 0x1p-96f, 0x1p126f);
+    if (__builtin_expect(other != 0, 0)) {
+        if (__builtin_amdgcn_inverse_ballot_w64(other)) r = __builtin_sqrtf(x);
     }
     return r;
 }
@@ -89,9 +90,9 @@ __device__ __forceinline__ float sqrt_rn(float x) {
 // lies in [2^-48, 2^63], inside the reciprocal's, so one test covers both.
 __device__ __forceinline__ float inv_sqrt_rn(float s) {
     float q = recip_fast(sqrt_fast(s));
-    const bool other = !sqrt_fast_ok(s);
-    if (__builtin_expect(__ballot(other) != 0, 0)) {
-        if (other) q = 1.0f / __builtin_sqrtf(s);
+    const uint64_t other = lanes_outside(s, 0x1p-96f, 0x1p126f);
+    if (__builtin_expect(other != 0, 0)) {
+        if (__builtin_amdgcn_inverse_ballot_w64(other)) q = 1.0f / __builtin_sqrtf(s);
     }
     return q;
 }
@@ -146,9 +147,10 @@ __device__ __forceinline__ void shade_vertex(const vr_shader_params &sh, float4 
             // 1/sqrt(d2) and the attenuation 1/(katt.d2 + 1), one range test
             float inv = recip_fast(sqrt_fast(d2));
             float att = recip_fast(ad);
-            const bool other = !(sqrt_fast_ok(d2) && recip_fast_ok(ad));
-            if (__builtin_expect(__ballot(other) != 0, 0)) {
-                if (other) {
+            const uint64_t other = lanes_outside(d2, 0x1p-96f, 0x1p126f) |
+                                   lanes_outside(__builtin_fabsf(ad), 0x1p-125f, 0x1p125f);
+            if (__builtin_expect(other != 0, 0)) {
+                if (__builtin_amdgcn_inverse_ballot_w64(other)) {
                     inv = 1.0f / __builtin_sqrtf(d2);
                     att = 1.0f / ad;
                 }
