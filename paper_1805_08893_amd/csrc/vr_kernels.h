@@ -652,25 +652,18 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
     }
 }
 
-// Unit base + workgroup index.
+// Units from base on: unit base + workgroup index (stride 0), or
+// grid-stride over every unit from base on (stride = the grid).  Grid-stride
+// serves the units of a dynamic draw beyond the fewest it can have within
+// the same launch; it is used without prefix outputs only, since the
+// look-back needs each unit's predecessor running or done.
 template <int NT, int MODE, int KIND>
-__global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh, uint32_t base) {
+__global__ __launch_bounds__(NT) void k_dedup(DrawArgs A, vr_shader_params sh, uint32_t base, uint32_t stride) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     if (base == 0) clear_counters(A);
     const uint32_t nb = launch_units(A, batch_count(A));
-    const uint32_t u = base + blockIdx.x;
-    if (u >= nb) return;
-    dedup_unit<NT, MODE, KIND>(A, sh, u, nb, smem);
-}
-
-// Every unit from base on, grid-stride: the part of a dynamic draw beyond
-// the fewest units it can have (without prefix outputs only: the look-back
-// needs each unit's predecessor running or done).
-template <int NT, int MODE, int KIND>
-__global__ __launch_bounds__(NT) void k_dedup_rest(DrawArgs A, vr_shader_params sh, uint32_t base) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const uint32_t nb = launch_units(A, batch_count(A));
-    for (uint32_t u = base + blockIdx.x; u < nb; u += gridDim.x) dedup_unit<NT, MODE, KIND>(A, sh, u, nb, smem);
+    for (uint64_t u = (uint64_t)base + blockIdx.x; u < nb; u += stride ? stride : nb)
+        dedup_unit<NT, MODE, KIND>(A, sh, (uint32_t)u, nb, smem);
 }
 
 // ---------------------------------------------------------------------------

@@ -245,24 +245,21 @@ vr_status check_args(vr_ctx *c, uint64_t num_indices, uint32_t num_vertices, con
 
 // A static draw's units are exactly known.  A dynamic draw has at least
 // ceil(T / N_pmax) units (exactly that many when every batch is full) and at
-// most the host-side bound: the first launch covers the fewest, a second
-// covers the rest, grid-stride over 8 workgroups per CU when the units may
-// come in any order (no prefix outputs), else one workgroup per unit.
+// most the host-side bound.  The launch has one workgroup per unit of the
+// fewest; without prefix outputs (units in any order) the same workgroups
+// take the rest grid-stride, else a second launch has one workgroup per
+// possible further unit.
 template <int NT, int MODE, int KIND>
 void launch_dedup(vr_ctx *c, const DrawArgs &A, const vr_shader_params &sh, uint32_t lds, uint64_t units) {
     uint64_t first = units;
     if (A.plan) first = std::min<uint64_t>(units, (A.T + A.batch_tris - 1) / A.batch_tris);
+    const bool stride = A.plan && !A.need_prefix && first > 0 && units > first;
     if (first)
-        hipLaunchKernelGGL((k_dedup<NT, MODE, KIND>), dim3((uint32_t)first), dim3(NT), lds, c->stream, A, sh, 0u);
-    if (units > first) {
-        if (A.need_prefix)
-            hipLaunchKernelGGL((k_dedup<NT, MODE, KIND>), dim3((uint32_t)(units - first)), dim3(NT), lds, c->stream, A,
-                               sh, (uint32_t)first);
-        else
-            hipLaunchKernelGGL((k_dedup_rest<NT, MODE, KIND>),
-                               dim3((uint32_t)std::min<uint64_t>(units - first, 8ull * c->num_cus)), dim3(NT), lds,
-                               c->stream, A, sh, (uint32_t)first);
-    }
+        hipLaunchKernelGGL((k_dedup<NT, MODE, KIND>), dim3((uint32_t)first), dim3(NT), lds, c->stream, A, sh, 0u,
+                           stride ? (uint32_t)first : 0u);
+    if (units > first && !stride)
+        hipLaunchKernelGGL((k_dedup<NT, MODE, KIND>), dim3((uint32_t)(units - first)), dim3(NT), lds, c->stream, A,
+                           sh, (uint32_t)first, 0u);
 }
 
 template <int MODE, int KIND>
