@@ -387,12 +387,23 @@ __device__ __forceinline__ const uint16_t *radix_passes(const uint32_t *s_keys, 
             const bool act = x < n;
             const uint32_t p = act ? src[x] : 0u;
             const uint32_t d = act ? ((s_keys[p] - kmin) >> (8 * pass)) & 0xFFu : 0u;
-            uint64_t peers = ballot(act);
+            // lanes with the same digit: for each bit, the lanes that agree
+            // on it are m where the bit is set and ~m where it is clear
+            const uint64_t act_m = ballot(act);
+            uint32_t plo = (uint32_t)act_m, phi = (uint32_t)(act_m >> 32);
+            const uint32_t nd = ~d;
 #pragma unroll
             for (int bit = 0; bit < 8; ++bit) {
-                const uint64_t m = ballot((d >> bit) & 1u);
-                peers &= ((d >> bit) & 1u) ? m : ~m;
+                // nx = ~0 where the bit is clear, 0 where it is set (one signed
+                // bit-field extract, kept opaque so that it is not rebuilt from
+                // compares and selects)
+                uint32_t nx;
+                asm volatile("v_bfe_i32 %0, %1, %2, 1" : "=v"(nx) : "v"(nd), "n"(bit));
+                const uint64_t m = ballot(nx == 0u);
+                plo &= (uint32_t)m ^ nx;
+                phi &= (uint32_t)(m >> 32) ^ nx;
             }
+            const uint64_t peers = ((uint64_t)phi << 32) | plo;
             const uint32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
             if (act && rk == 0) s_c8[d * Gp + r * NW + w] = (uint8_t)__popcll(peers);
