@@ -496,8 +496,8 @@ def serving_benchmark(stage, seed=11, n=2000, rate=500.0, budget=64 << 30, small
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-passes", type=int, default=6, help="passes of the full step the CPU oracle times (about 10 s)")
     ap.add_argument("--level", type=int, default=8, help="icosphere subdivision level")
@@ -543,7 +543,7 @@ def main():
     mesh, sp = W.icosphere8_hilbert_phong8(level=args.level)
     T, V = mesh.num_tris, mesh.num_verts
     if args.sweep:
-        sweep(mesh, sp, reps=max(3, args.steps))
+        sweep(mesh, sp, reps=max(3, min(args.steps, 20)))
         return
     U = int(len(np.unique(mesh.indices)))
     idx = torch.from_numpy(mesh.indices.view(np.int32)).cuda()
@@ -604,7 +604,8 @@ def main():
     for k in range(args.steps):
         step(ev[k])
     torch.cuda.synchronize()
-    ktimes = np.array(vr.vr_kernel_times(stage.ctx), dtype=np.float64).reshape(args.steps, len(names))
+    ktimes = np.array(vr.vr_kernel_times(stage.ctx, cap=len(names) * args.steps + 16),
+                      dtype=np.float64).reshape(args.steps, len(names))
     vr.vr_set_kernel_timing(stage.ctx, False)
     st, _ = stage.sync()
     stage.check(st)
