@@ -44,9 +44,9 @@ __device__ __forceinline__ float xrow(const float *M, int r, float x, float y, f
 // sequence gives the same bits:
 //  * 1/x for |x| in [2^-125, 2^125]: the hardware reciprocal (within one ulp)
 //    and one Newton-Raphson step on the exact FMA residual 1 - x.y;
-//  * sqrt(x) for x in [2^-96, 2^126]: the hardware square root (within one
-//    ulp), replaced by the neighbour s -/+ 1 ulp that the sign of the FMA
-//    residual x - s'.s selects.
+//  * sqrt(x) for x in [2^-96, 2^126]: s = x.y and h = y/2 from the hardware
+//    reciprocal square root y, then one Newton step s + h.(x - s.s) on the
+//    exact FMA residual.
 // Every other operand (zero, denormal, huge, negative, inf, NaN) takes the
 // compiler's sequence.  vr_math_selftest compares both against the
 // compiler's sequences bit for bit over all 2^32 float32 operands
@@ -56,10 +56,9 @@ __device__ __forceinline__ float recip_fast(float x) {
     return __builtin_fmaf(__builtin_fmaf(-x, y, 1.0f), y, y);
 }
 __device__ __forceinline__ float sqrt_fast(float x) {
-    const float s = __builtin_amdgcn_sqrtf(x);
-    const float lo = __uint_as_float(__float_as_uint(s) - 1u), hi = __uint_as_float(__float_as_uint(s) + 1u);
-    const float r = __builtin_fmaf(-lo, s, x) <= 0.0f ? lo : s;
-    return __builtin_fmaf(-hi, s, x) > 0.0f ? hi : r;
+    const float y = __builtin_amdgcn_rsqf(x);
+    const float s = x * y, h = 0.5f * y;
+    return __builtin_fmaf(__builtin_fmaf(-s, s, x), h, s);
 }
 
 // Lanes whose operand lies outside [lo, hi] (NaN included), as a wavefront
