@@ -47,6 +47,18 @@ def shader_flops(sp):
     return mvp
 
 
+def host_cpu_model():
+    """The host CPU's model name (Linux), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def kernel_source_sha():
     """Hash of the kernel sources: HBM-traffic counters are used only when they
     were taken on exactly these sources."""
@@ -661,7 +673,8 @@ def main():
                 tris_cpu += T
         cpu = {"value": tris_cpu / t_cpu, "unit": "triangles/s", "cores": 1, "kind": "oracle",
                "sample": f"{args.cpu_passes} pass(es) of the full step (5 strategies x {T} triangles), "
-                         f"single-threaded C oracle, {t_cpu:.1f} s"}
+                         f"single-threaded C oracle, {t_cpu:.1f} s",
+               "host_cpu": host_cpu_model(), "host_threads": len(os.sched_getaffinity(0))}
 
     cold = None
     if not args.only and not args.no_extra:
