@@ -103,26 +103,33 @@ __device__ __forceinline__ void write_unit(const DrawArgs &A, uint32_t t0, uint3
                                            uint32_t tid) {
     const uint32_t ncorner = 3 * ntri;
     if (A.corners) {
-        // four rows per lane at a time, so that their LDS reads overlap
-        f4 *dst = A.corners + 9ull * t0;
-        const uint32_t cnt = 9 * ntri;
-        uint32_t q = tid;
-        for (; q + 3 * NT < cnt; q += 4 * NT) {
-            uint32_t at[4];
-            f4 row[4];
+        // float4 q of the span is part q % 3 of corner q / 3.  Lane tid takes
+        // q = tid + NT i; NT is a power of two, so NT = r (mod 3) with r = 1
+        // or 2, and for i = 3 m + j the corner is NT m + kj[j] and the part
+        // pj[j], both fixed per lane: no division in the loop.  Three rows per
+        // lane at a time, so that their LDS reads overlap.
+        constexpr uint32_t r = NT % 3;
+        static_assert(r != 0, "the workgroup size is a power of two");
+        uint32_t kj[3], pj[3];
 #pragma unroll
-            for (uint32_t i = 0; i < 4; ++i) {
-                const uint32_t x = q + i * NT, k = x / 3;
-                at[i] = 3 * (uint32_t)s_local[k] + (x - 3 * k);
-            }
-#pragma unroll
-            for (uint32_t i = 0; i < 4; ++i) row[i] = s_sv[at[i]];
-#pragma unroll
-            for (uint32_t i = 0; i < 4; ++i) __builtin_nontemporal_store(row[i], dst + q + i * NT);
+        for (uint32_t j = 0; j < 3; ++j) {
+            const uint32_t m = tid + r * j;
+            kj[j] = (NT - r) / 3 * j + m / 3;
+            pj[j] = m % 3;
         }
-        for (; q < cnt; q += NT) {
-            const uint32_t k = q / 3, part = q - 3 * k;
-            __builtin_nontemporal_store(s_sv[3 * (uint32_t)s_local[k] + part], dst + q);
+        f4 *dst = A.corners + 9ull * t0;
+        const uint32_t cnt = 9 * ntri, klast = ncorner - 1;
+        for (uint32_t q = tid, kb = 0; q < cnt; q += 3 * NT, kb += NT) {
+            uint32_t at[3];
+            f4 row[3];
+            // rows past the span read the last corner (kept in bounds) and are not stored
+#pragma unroll
+            for (uint32_t j = 0; j < 3; ++j) at[j] = 3 * (uint32_t)s_local[min(kb + kj[j], klast)] + pj[j];
+#pragma unroll
+            for (uint32_t j = 0; j < 3; ++j) row[j] = s_sv[at[j]];
+#pragma unroll
+            for (uint32_t j = 0; j < 3; ++j)
+                if (q + j * NT < cnt) __builtin_nontemporal_store(row[j], dst + q + j * NT);
         }
     }
     if (A.tris || A.local_idx) {
