@@ -413,7 +413,8 @@ __device__ __forceinline__ const uint16_t *radix_passes(const uint32_t *s_keys, 
             const uint64_t peers = ((uint64_t)phi << 32) | plo;
             const uint32_t rk = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
-            if (act && rk == 0) s_c8[d * Gp + r * NW + w] = (uint8_t)__popcll(peers);
+            // digit x group index in 24-bit products (full-rate multiplies)
+            if (act && rk == 0) s_c8[__umul24(d, Gp) + r * NW + w] = (uint8_t)__popcll(peers);
             dig[r] = d;
             rank[r] = rk;
             pos[r] = p;
@@ -444,7 +445,7 @@ __device__ __forceinline__ const uint16_t *radix_passes(const uint32_t *s_keys, 
         for (uint32_t r = 0; r < RR; ++r) {
             if (RR == 8 && r >= R) break;
             const uint32_t x = r * NT + tid;
-            if (x < n) dst[s_o16[dig[r] * Gp + r * NW + w] + rank[r]] = (uint16_t)pos[r];
+            if (x < n) dst[s_o16[__umul24(dig[r], Gp) + r * NW + w] + rank[r]] = (uint16_t)pos[r];
         }
         __syncthreads();
         uint16_t *t = src;
@@ -735,7 +736,7 @@ __device__ __forceinline__ uint32_t ballot_round(const DrawArgs &A, uint32_t t0,
         const uint32_t gt = min(21u, t1 - cur);
         const uint32_t nc = 3 * gt;
         const bool act = lane < nc;
-        const uint32_t pos = 3 * (cur - t0) + lane;
+        const uint32_t pos = __umul24(3u, cur - t0) + lane;   // cur - t0 < 2^24 (a batch)
         const uint32_t k = act ? (pos < pre ? s_keys[pos] : fetch_index(A, 3ull * cur + lane)) : kEmpty;
         // one vote per distinct value, lowest unresolved lane first: that
         // lane is the value's first occurrence in the group
