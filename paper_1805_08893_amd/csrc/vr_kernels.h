@@ -64,13 +64,37 @@ __device__ __forceinline__ void batch_range(const DrawArgs &A, uint32_t b, uint3
 
 // Index fetch with the range check fused in: an index >= V raises
 // VR_ERR_INDEX_RANGE and is replaced by 0 so no access leaves the buffers.
-__device__ __forceinline__ uint32_t fetch_index(const DrawArgs &A, uint64_t pos) {
-    uint32_t k = A.idx[pos];
+__device__ __forceinline__ uint32_t checked_index(const DrawArgs &A, uint32_t k) {
     if (k >= A.V) {
         raise_error(A.err, VR_ERR_INDEX_RANGE);
         k = 0;
     }
     return k;
+}
+
+__device__ __forceinline__ uint32_t fetch_index(const DrawArgs &A, uint64_t pos) {
+    return checked_index(A, A.idx[pos]);
+}
+
+// The indices idx[base .. base + n) into dst[0 .. n), checked as
+// fetch_index does, by NT threads; each thread issues three loads before it
+// uses the first, so that their latencies overlap.
+template <uint32_t NT>
+__device__ __forceinline__ void load_indices(const DrawArgs &A, uint64_t base, uint32_t n, uint32_t *dst,
+                                             uint32_t tid) {
+    for (uint32_t i0 = 0; i0 < n; i0 += 3 * NT) {
+        uint32_t v[3];
+#pragma unroll
+        for (uint32_t r = 0; r < 3; ++r) {
+            const uint32_t i = i0 + r * NT + tid;
+            v[r] = i < n ? A.idx[base + i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < 3; ++r) {
+            const uint32_t i = i0 + r * NT + tid;
+            if (i < n) dst[i] = checked_index(A, v[r]);
+        }
+    }
 }
 
 // Shades the vertex whose 32 input bytes are (a, b) into dst[0..2].
@@ -488,7 +512,7 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
             n = 0;
         }
 
-        for (uint32_t i = tid; i < n; i += NT) s_keys[i] = fetch_index(A, 3ull * t0 + i);
+        load_indices<NT>(A, 3ull * t0, n, s_keys, tid);
 
         uint32_t inv;
         if (MODE == kSort) {
@@ -825,7 +849,7 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
     uint32_t *s_new = s_keys + cap;
     uint8_t *s_map = (uint8_t *)(s_new + 2 * kWave);
     const uint32_t pre = min(3 * (t1 - t0), cap);
-    for (uint32_t i = lane; i < pre; i += kWave) s_keys[i] = fetch_index(A, 3ull * t0 + i);
+    load_indices<kWave>(A, 3ull * t0, pre, s_keys, lane);
     wave_sync_lds();
     uint32_t vbase = 0, ubase = b;
     RoundState st;
