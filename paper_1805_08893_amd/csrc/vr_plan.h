@@ -97,16 +97,19 @@ __global__ __launch_bounds__(256) void k_plan_check(PlanArgs P, uint32_t *plan) 
             plan[1 + gridDim.x] = P.T;
         }
     }
+    // every load is issued before the first is checked, so their latencies overlap
     uint32_t key[kCheckPer];
 #pragma unroll
     for (uint32_t k = 0; k < kCheckPer; ++k) {
         const uint32_t i = tid + 256 * k;
-        uint32_t v = i < n ? P.idx[3ull * t0 + i] : 0u;
-        if (i < n && v >= P.V) {
+        key[k] = i < n ? P.idx[3ull * t0 + i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kCheckPer; ++k) {
+        if (tid + 256 * k < n && key[k] >= P.V) {
             raise_error(P.err, VR_ERR_INDEX_RANGE);
-            v = 0;
+            key[k] = 0;
         }
-        key[k] = v;
     }
     for (uint32_t q = tid; q < (1u << kCheckBits); q += 256) s_tab[q] = kEmpty;
     __syncthreads();
@@ -162,13 +165,25 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
     const uint32_t r1 = min(P.T, c0 + kNextBlock + P.tmax);
     const uint32_t n = 3 * (r1 - c0);
 
-    for (uint32_t i = tid; i < n; i += 256) {
-        uint32_t v = P.idx[3ull * c0 + i];
-        if (v >= P.V) {
-            raise_error(P.err, VR_ERR_INDEX_RANGE);
-            v = 0;
+    // three loads per thread issued before the first is checked (latencies overlap)
+    for (uint32_t i0 = 0; i0 < n; i0 += 3 * 256) {
+        uint32_t v[3];
+#pragma unroll
+        for (uint32_t r = 0; r < 3; ++r) {
+            const uint32_t i = i0 + r * 256 + tid;
+            v[r] = i < n ? P.idx[3ull * c0 + i] : 0u;
         }
-        s_key[i] = v;
+#pragma unroll
+        for (uint32_t r = 0; r < 3; ++r) {
+            const uint32_t i = i0 + r * 256 + tid;
+            if (i < n) {
+                if (v[r] >= P.V) {
+                    raise_error(P.err, VR_ERR_INDEX_RANGE);
+                    v[r] = 0;
+                }
+                s_key[i] = v[r];
+            }
+        }
     }
     for (uint32_t s = tid; s < kNextSlots; s += 256) {
         s_tab[s] = kEmpty;
