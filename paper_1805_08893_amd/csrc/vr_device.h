@@ -138,6 +138,9 @@ __device__ __forceinline__ void shade_vertex(const vr_shader_params &sh, float4 
         const float wz = xrow(sh.model, 2, px, py, pz);
         float vx = sh.eye[0] - wx, vy = sh.eye[1] - wy, vz = sh.eye[2] - wz;
         normalize3(vx, vy, vz);
+        // fma(2 ndl, n', -l) = fma(ndl, 2 n', -l) bit for bit: doubling is
+        // exact, so both see the same exact product
+        const float m2x = 2.0f * mx, m2y = 2.0f * my, m2z = 2.0f * mz;
         for (uint32_t l = 0; l < sh.num_lights; ++l) {
             const float *L = sh.lights[l];
             const float dx = L[0] - wx, dy = L[1] - wy, dz = L[2] - wz;
@@ -156,15 +159,19 @@ __device__ __forceinline__ void shade_vertex(const vr_shader_params &sh, float4 
             }
             const float lx = dx * inv, ly = dy * inv, lz = dz * inv;
             const float ndl = dot3(mx, my, mz, lx, ly, lz);
-            const float df = ndl > 0.0f ? ndl : 0.0f;
-            const float t = 2.0f * ndl;
-            const float rx = __builtin_fmaf(t, mx, -lx);
-            const float ry = __builtin_fmaf(t, my, -ly);
-            const float rz = __builtin_fmaf(t, mz, -lz);
+            // ndl > 0 ? ndl : 0 as one v_max_f32 with 0: ndl is an arithmetic
+            // result (never a signalling NaN), NaN gives 0 and -0 gives +0, as
+            // the select does; written out so that no canonicalising max precedes it
+            float df;
+            asm("v_max_f32 %0, 0, %1" : "=v"(df) : "v"(ndl));
+            const float kdf = sh.kd * df;
+            const float rx = __builtin_fmaf(ndl, m2x, -lx);
+            const float ry = __builtin_fmaf(ndl, m2y, -ly);
+            const float rz = __builtin_fmaf(ndl, m2z, -lz);
             const float rv = dot3(rx, ry, rz, vx, vy, vz);
             float sp = rv > 0.0f ? rv : 0.0f;
             for (uint32_t s = 0; s < sh.spec_squarings; ++s) sp = sp * sp;
-            const float k = att * __builtin_fmaf(sh.ks, sp, sh.kd * df);
+            const float k = att * __builtin_fmaf(sh.ks, sp, kdf);
             cr = __builtin_fmaf(k, L[3], cr);
             cg = __builtin_fmaf(k, L[4], cg);
             cb = __builtin_fmaf(k, L[5], cb);
