@@ -74,3 +74,34 @@ def test_fallback_ranges_match_oracle(stage, scale, katt):
         gn, en = np.isnan(got), np.isnan(exp)
         np.testing.assert_array_equal(gn, en)
         np.testing.assert_array_equal(got[~gn].view(np.uint32), exp[~en].view(np.uint32))
+
+
+@pytest.mark.parametrize("kind", [W.SHADER_MVP, W.SHADER_PHONG], ids=["mvp", "phong"])
+def test_zero_normals_match_oracle(stage, kind):
+    """Zero normals: the normalisation's square root is 0, so 1/sqrt is inf
+    and the normal outputs are NaN (0 x inf) on both sides; the rest of
+    every corner is compared bitwise."""
+    from paper_1805_08893_amd import vr
+    m = W.grid_mesh(16, 16, seed=33, order="hilbert")
+    v = m.vertices.copy()
+    v[::3, 3] = 0.0   # every third vertex: n = (0, 0, 0)
+    v[::3, 4] = 0.0
+    v[::3, 5] = 0.0
+    mesh = W.Mesh(m.name + "_zero_normals", m.indices, v)
+    sp = W.shader_for_mesh(mesh, kind, 34, num_lights=4 if kind == W.SHADER_PHONG else 0)
+    idx = torch.from_numpy(np.ascontiguousarray(mesh.indices).view(np.int32)).cuda()
+    vtx = torch.from_numpy(np.ascontiguousarray(mesh.vertices)).cuda()
+    for name, strategy, bt, nu in (("naive", vr.VR_NAIVE, 1, 0), ("dyn_sort", vr.VR_DYN_SORT, 128, 128)):
+        print(f"[ranges] zero normals kind {kind} {name}", flush=True)
+        res = stage.draw(idx, vtx, sp, strategy, bt, dict(max_unique=nu), corners=True)
+        st, _ = stage.sync()
+        assert st == vr.VR_OK, vr.vr_last_error(stage.ctx)
+        got = res["corners"].cpu().numpy()
+        rc, ora = vro.process_draw(mesh.indices, mesh.vertices, sp, strategy, bt, {"max_unique": nu},
+                                   tris=False, verts=False, local_idx=False, units=False)
+        assert rc == vro.OK
+        exp = ora["corners"]
+        gn, en = np.isnan(got), np.isnan(exp)
+        assert en.any()   # the case reaches the non-finite path
+        np.testing.assert_array_equal(gn, en)
+        np.testing.assert_array_equal(got[~gn].view(np.uint32), exp[~en].view(np.uint32))
