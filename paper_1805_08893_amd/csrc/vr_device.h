@@ -141,6 +141,10 @@ __device__ __forceinline__ void shade_vertex(const vr_shader_params &sh, float4 
         // fma(2 ndl, n', -l) = fma(ndl, 2 n', -l) bit for bit: doubling is
         // exact, so both see the same exact product
         const float m2x = 2.0f * mx, m2y = 2.0f * my, m2z = 2.0f * mz;
+        // with 0 <= katt <= 1/2, d2 in [2^-96, 2^126] gives katt.d2 + 1 in
+        // [1, 2^125] (the fma rounds 2^125 + 1 down to 2^125), inside the
+        // reciprocal's short range: its own range test is then not needed
+        const bool katt_small = sh.katt >= 0.0f && sh.katt <= 0.5f;
         for (uint32_t l = 0; l < sh.num_lights; ++l) {
             const float *L = sh.lights[l];
             const float dx = L[0] - wx, dy = L[1] - wy, dz = L[2] - wz;
@@ -149,8 +153,8 @@ __device__ __forceinline__ void shade_vertex(const vr_shader_params &sh, float4 
             // 1/sqrt(d2) and the attenuation 1/(katt.d2 + 1), one range test
             float inv = recip_fast(sqrt_fast(d2));
             float att = recip_fast(ad);
-            const uint64_t other = lanes_outside(d2, 0x1p-96f, 0x1p126f) |
-                                   lanes_outside(__builtin_fabsf(ad), 0x1p-125f, 0x1p125f);
+            uint64_t other = lanes_outside(d2, 0x1p-96f, 0x1p126f);
+            if (!katt_small) other |= lanes_outside(__builtin_fabsf(ad), 0x1p-125f, 0x1p125f);
             if (__builtin_expect(other != 0, 0)) {
                 if (__builtin_amdgcn_inverse_ballot_w64(other)) {
                     inv = 1.0f / __builtin_sqrtf(d2);
