@@ -885,10 +885,11 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
     if (lane == 0 && A.agg) A.agg[b] = ((unsigned long long)r << 32) | inv;
 }
 
-// Four wavefronts per workgroup, one batch each (batch 4 * workgroup +
-// wavefront); `stride` is the per-wavefront LDS area.  Larger workgroups keep
-// more wavefronts resident than one-wavefront workgroups would.
-constexpr uint32_t kBallotWaves = 4;
+// Two wavefronts per workgroup, one batch each (batch 2 * workgroup +
+// wavefront); `stride` is the per-wavefront LDS area.  Two measured faster
+// than four and eight; one-wavefront workgroups keep fewer wavefronts
+// resident.
+constexpr uint32_t kBallotWaves = 2;
 
 template <int KIND>
 __global__ __launch_bounds__(kBallotWaves * 64) void k_ballot(DrawArgs A, vr_shader_params sh, uint32_t stride) {
