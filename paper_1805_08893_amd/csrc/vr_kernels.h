@@ -887,8 +887,7 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
 
 // Two wavefronts per workgroup, one batch each (batch 2 * workgroup +
 // wavefront); `stride` is the per-wavefront LDS area.  Two measured faster
-// than four and eight; one-wavefront workgroups keep fewer wavefronts
-// resident.
+// than four and eight, and about as fast as one.
 constexpr uint32_t kBallotWaves = 2;
 
 template <int KIND>
