@@ -344,6 +344,83 @@ def test_phong_specular_exponent():
         assert abs(o32[9] - expect) <= 1e-6 * max(expect, 1e-30) * (2 ** s) + 1e-12
 
 
+# A model matrix that is neither symmetric nor an involution: a cyclic axis
+# permutation plus a translation, all entries powers of two or zero, so the
+# world position is exact.  Read column-major or transposed it gives another
+# point.  w = (p.y + 1, p.z - 2, p.x + 1/2).
+PERM_MODEL = np.array([0, 1, 0, 1.0,
+                       0, 0, 1, -2.0,
+                       1, 0, 0, 0.5], np.float32)
+
+
+def _perm_world(p):
+    return np.float32([p[1] + 1.0, p[2] - 2.0, p[0] + 0.5])
+
+
+def _phong_on_axis(model, p, offsets, colours, katt, ambient, kd=0.75, ks=0.25):
+    """Phong with lights at world offsets (0, 0, dz) above the vertex's world
+    position w = model (p, 1), the normal +z and the eye at w + (0, 0, 5)."""
+    sp = _identity_shader(W.SHADER_PHONG)
+    sp.model = np.asarray(model, np.float32)
+    sp.kd, sp.ks, sp.katt = kd, ks, katt
+    sp.ambient = np.float32(ambient)
+    sp.spec_squarings = 5
+    w = _perm_world(p) if model is PERM_MODEL else np.float32(p)
+    sp.eye = w + np.float32([0, 0, 5])
+    lights = np.zeros((16, 6), np.float32)
+    for l, (dz, c) in enumerate(zip(offsets, colours)):
+        lights[l, :3] = w + np.float32([0, 0, dz])
+        lights[l, 3:] = c
+    sp.lights = lights
+    sp.num_lights = len(offsets)
+    return vro.shade(sp, _vbuf(p))[0]
+
+
+def test_phong_world_position_uses_row_major_model():
+    """The lighting sees the world position model (p, 1) with the 3x4 model
+    matrix stored row-major.  With the light 2 above w along the normal and
+    the eye above it, diffuse = specular = 1 and att = 1/(1 + 1/4 * 4) = 1/2,
+    so the colour is ambient + (1/2) * light colour exactly; any other world
+    position puts the light off the normal and changes it."""
+    for p in ((0.5, -1.25, 3.0), (-2.0, 0.25, 0.5), (1.0, 2.0, -0.75)):
+        out = _phong_on_axis(PERM_MODEL, p, [2.0], [(1.0, 0.5, 2.0)], 0.25, (0.25, 0.125, 0.0))
+        np.testing.assert_array_equal(out[9:], np.float32([0.75, 0.375, 1.0]))
+        # the model matrix feeds lighting only: clip = mvp (p, 1) = (p, 1)
+        np.testing.assert_array_equal(out[:4], np.float32([*p, 1.0]))
+
+
+def test_phong_each_light_with_its_own_position_colour_and_attenuation():
+    """Three lights on the normal at heights 1, 3 and 1 with katt = 7:
+    att = 1/(1 + 7) = 1/8, 1/(1 + 63) = 1/64 and 1/8 (powers of two), and
+    diffuse = specular = 1 with kd + ks = 1, so light l adds att_l * colour_l
+    exactly.  Colours are distinct powers of two per channel, so dropping or
+    repeating a light, or pairing a position with another light's colour,
+    changes the sum."""
+    cols = [(2.0, 0.0, 0.0), (0.0, 4.0, 0.0), (0.0, 0.0, 8.0)]
+    out = _phong_on_axis(PERM_MODEL, (0.5, -1.25, 3.0), [1.0, 3.0, 1.0], cols, 7.0, (0.0, 0.0, 0.0))
+    np.testing.assert_array_equal(out[9:], np.float32([2.0 / 8, 4.0 / 64, 8.0 / 8]))
+    # the first light alone, and the first two: the loop runs l = 0 .. L-1
+    out = _phong_on_axis(PERM_MODEL, (0.5, -1.25, 3.0), [1.0], cols[:1], 7.0, (0.0, 0.0, 0.0))
+    np.testing.assert_array_equal(out[9:], np.float32([0.25, 0.0, 0.0]))
+    out = _phong_on_axis(PERM_MODEL, (0.5, -1.25, 3.0), [1.0, 3.0], cols[:2], 7.0, (0.0, 0.0, 0.0))
+    np.testing.assert_array_equal(out[9:], np.float32([0.25, 0.0625, 0.0]))
+
+
+def test_phong_lights_accumulate_in_order():
+    """The colour is accumulated light 0 first, one rounded fma per light.
+    With ambient 1, k = 1 per light (katt = 0, light on the normal) and
+    contributions of 3/4 and 1/2 ulp(1): in order 0, 1 the x channel rounds
+    1 + 3/4 ulp up to 1 + ulp, then 1 + 3/2 ulp ties to even 1 + 2 ulp; the
+    y channel takes 1/2 ulp first (a tie, back to 1) and then 3/4 ulp, giving
+    1 + ulp.  The reverse order swaps the two results."""
+    ulp = 2.0 ** -23
+    cols = [(0.75 * ulp, 0.5 * ulp, 0.0), (0.5 * ulp, 0.75 * ulp, 0.0)]
+    out = _phong_on_axis(PERM_MODEL, (0.5, -1.25, 3.0), [1.0, 2.0], cols, 0.0, (1.0, 1.0, 1.0))
+    np.testing.assert_array_equal(out[9:], np.float32([1.0 + 2 * ulp, 1.0 + ulp, 1.0]))
+    out = _phong_on_axis(PERM_MODEL, (0.5, -1.25, 3.0), [2.0, 1.0], cols[::-1], 0.0, (1.0, 1.0, 1.0))
+    np.testing.assert_array_equal(out[9:], np.float32([1.0 + ulp, 1.0 + 2 * ulp, 1.0]))
+
+
 def test_offset_reaches_fixed_point():
     """64 relaxation steps converge to the real root of
     c3 h^3 + c2 h^2 + (c1 - 1) h + dot(cvec, p) = 0 (contraction ~0.75)."""
