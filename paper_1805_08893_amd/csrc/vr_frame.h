@@ -31,6 +31,7 @@ struct DrawDesc {
     uint32_t V, T, batch_tris, num_batches;
     uint32_t shader, mode, kind;
     uint32_t max_idx, max_uniq, hash_bits, probes;
+    uint32_t slot_cap;   // aggregate slots the host reserved for the draw's batches
 };
 
 // Batches of a plan that start before triangle T.  A plan built for a
@@ -48,27 +49,35 @@ __device__ __forceinline__ uint32_t plan_prefix_batches(const uint32_t *plan, ui
     return hi;
 }
 
-// Units (workgroup tasks) and aggregate slots of a draw.
-__device__ __forceinline__ void frame_draw_units(const DrawDesc &D, uint32_t &units, uint32_t &slots) {
+// Units (workgroup tasks) and aggregate slots of a draw.  A plan with more
+// batches than the host reserved slots for (one built with a smaller N_u or
+// N_pmax than the draw states) raises VR_ERR_CAPACITY and is cut to the
+// reserved slots, so no aggregate lands outside the draw's range.
+__device__ __forceinline__ void frame_draw_units(const DrawDesc &D, uint32_t &units, uint32_t &slots,
+                                                 uint32_t *err) {
     if (D.mode == kFrameNaive) {
         units = slots = (uint32_t)((3ull * D.T + 255) / 256);
         return;
     }
-    const uint32_t nb = D.T == 0 ? 0u : (D.plan ? plan_prefix_batches(D.plan, D.T) : D.num_batches);
+    uint32_t nb = D.T == 0 ? 0u : (D.plan ? plan_prefix_batches(D.plan, D.T) : D.num_batches);
+    if (nb > D.slot_cap) {
+        raise_error(err, VR_ERR_CAPACITY);
+        nb = D.slot_cap;
+    }
     slots = nb;
     units = D.mode == kFrameBallot ? (nb + 3) / 4 : nb;   // four wavefronts, four ballot batches
 }
 
 // One workgroup: per-draw unit and slot bases (exclusive scans), totals last.
 __global__ __launch_bounds__(1024) void k_frame_prepare(const DrawDesc *draws, uint32_t n, uint32_t *unit_base,
-                                                        uint32_t *slot_base) {
+                                                        uint32_t *slot_base, uint32_t *err) {
     __shared__ uint32_t tmp[16];
     const uint32_t E = (n + 1023) / 1024;
     const uint32_t lo = min(n, threadIdx.x * E), hi = min(n, lo + E);
     uint32_t su = 0, ss = 0;
     for (uint32_t d = lo; d < hi; ++d) {
         uint32_t u, s;
-        frame_draw_units(draws[d], u, s);
+        frame_draw_units(draws[d], u, s, err);
         su += u;
         ss += s;
     }
@@ -77,7 +86,7 @@ __global__ __launch_bounds__(1024) void k_frame_prepare(const DrawDesc *draws, u
     uint32_t rs = block_excl_scan<1024>(ss, tmp, ts);
     for (uint32_t d = lo; d < hi; ++d) {
         uint32_t u, s;
-        frame_draw_units(draws[d], u, s);
+        frame_draw_units(draws[d], u, s, err);
         unit_base[d] = ru;
         slot_base[d] = rs;
         ru += u;

@@ -411,7 +411,7 @@ struct FrameLaunch {
 
 void enqueue_frame_kernels(const FrameLaunch &L, hipStream_t s) {
     if (L.n == 0) return;
-    hipLaunchKernelGGL(k_frame_prepare, dim3(1), dim3(1024), 0, s, L.draws, L.n, L.unit_base, L.slot_base);
+    hipLaunchKernelGGL(k_frame_prepare, dim3(1), dim3(1024), 0, s, L.draws, L.n, L.unit_base, L.slot_base, L.err);
     hipLaunchKernelGGL(k_frame, dim3(L.grid), dim3(kFrameNT), L.lds_total, s, L.draws, L.n, L.shaders,
                        (const uint32_t *)L.unit_base, (const uint32_t *)L.slot_base, L.agg, L.unit_lds,
                        L.ballot_stride, L.err, L.total_inv);
@@ -495,6 +495,7 @@ vr_status describe_draw(vr_ctx *c, const vr_draw &D, const vr_shader_params &sh,
         need.units += (3 * T + 255) / 256;
     } else {
         const uint64_t nb = is_dynamic(D.strategy) ? dyn_batch_bound(T, r.nu, D.batch_tris) : X.num_batches;
+        X.slot_cap = (uint32_t)std::min<uint64_t>(nb, 0xFFFFFFFFull);
         need.slots += nb;
         if (X.mode == kFrameBallot) {
             need.units += (nb + 3) / 4;

@@ -145,3 +145,38 @@ def test_frame_argument_errors(stage):
     assert vr.vr_process_draws(stage.ctx, bad, shaders) == vr.VR_ERR_ARG
     assert vr.vr_process_draws(stage.ctx, [], shaders) == vr.VR_OK
     assert stage.sync()[0] == vr.VR_OK
+
+
+def test_frame_plan_with_more_batches_than_reserved_is_capacity_error(stage):
+    """A dynamic draw whose plan was built with a smaller N_u than the draw
+    states has more batches than the frame reserved aggregate slots for: the
+    frame raises VR_ERR_CAPACITY instead of writing past them, and the
+    context works normally afterwards."""
+    from paper_1805_08893_amd import vr
+    mesh = W.grid_mesh(60, 60, 5, "random")
+    sp = W.shader_for_mesh(mesh, W.SHADER_MVP, 5)
+    idx, vtx = _dev(mesh.indices), _dev(mesh.vertices)
+    small = torch.empty(mesh.num_tris + 2, dtype=torch.int32, device="cuda")
+    assert vr.vr_plan_dynamic(stage.ctx, idx, mesh.num_verts, 3, 341, small) == vr.VR_OK
+    assert stage.sync()[0] == vr.VR_OK
+    B = int(small[0].item())
+    assert B > mesh.num_tris // 85 + 1          # beyond the bound for N_u = 256, N_pmax = 341
+    corners = torch.empty((3 * mesh.num_tris, 12), dtype=torch.float32, device="cuda")
+    d = vr.make_draw(idx, vtx, 0, vr.VR_DYN_HASH, 341, corners, max_unique=256, plan=small)
+    print("case frame foreign plan", flush=True)
+    rc, fr = vr.vr_frame_create(stage.ctx, [d], [sp])
+    assert rc == vr.VR_OK, vr.vr_last_error(stage.ctx)
+    assert vr.vr_frame_run(fr) == vr.VR_OK
+    st, _ = stage.sync()
+    vr.vr_frame_destroy(fr)
+    assert st == vr.VR_ERR_CAPACITY
+    # the same draw with its own plan afterwards is exact
+    plan = torch.empty(mesh.num_tris + 2, dtype=torch.int32, device="cuda")
+    assert vr.vr_plan_dynamic(stage.ctx, idx, mesh.num_verts, 256, 341, plan) == vr.VR_OK
+    d = vr.make_draw(idx, vtx, 0, vr.VR_DYN_HASH, 341, corners, max_unique=256, plan=plan)
+    assert vr.vr_process_draws(stage.ctx, [d], [sp]) == vr.VR_OK
+    st, _ = stage.sync()
+    assert st == vr.VR_OK
+    rc, ora = vro.process_draw(mesh.indices, mesh.vertices, sp, vro.DYN_HASH, 341, {"max_unique": 256},
+                               tris=False, verts=False, local_idx=False, units=False)
+    np.testing.assert_array_equal(corners.cpu().numpy().view(np.uint32), ora["corners"].view(np.uint32))

@@ -179,13 +179,19 @@ def test_plan_reuse_matches_inline_plan(stage):
 
 
 def test_launch_shape_never_changes_results(stage):
+    """Workgroup size, hash-table size and probe count change the launch
+    only: every shape gives the oracle's outputs bit for bit, and hash and
+    parallel hash give the same ids."""
     mesh = W.icosphere_mesh(4, 12, "random")
     sp = W.shader_for_mesh(mesh, W.SHADER_MVP, 12)
     ref = None
     for strategy in (vro.DYN_HASH, vro.DYN_PHASH, vro.DYN_SORT):
+        rc, ora = vro.process_draw(mesh.indices, mesh.vertices, sp, strategy, 341, {"max_unique": 256})
+        assert rc == vro.OK
         for wg, slots, probes in ((0, 0, 0), (64, 256, 1), (512, 4096, 64), (128, 256, 0)):
             _log(f"case shape s={strategy} wg={wg} slots={slots} probes={probes}")
             g = gpu_draw(stage, mesh, sp, strategy, 341, 256, wg_size=wg, hash_slots=slots, hash_probes=probes)
+            compare(g, ora)
             if strategy == vro.DYN_SORT:
                 continue
             if ref is None:

@@ -105,3 +105,25 @@ def test_zero_normals_match_oracle(stage, kind):
         assert en.any()   # the case reaches the non-finite path
         np.testing.assert_array_equal(gn, en)
         np.testing.assert_array_equal(got[~gn].view(np.uint32), exp[~en].view(np.uint32))
+
+
+def test_phong_hand_cases_on_gpu(stage):
+    """The exact Phong cases that pin the oracle (row-major model matrix,
+    each light's own position, colour and attenuation, accumulation from
+    light 0), shaded by the library: naive and static hash on a draw whose
+    triangles all use one vertex."""
+    from paper_1805_08893_amd import vr
+    from test_oracle_pins import PERM_MODEL, PHONG_HAND_CASES, phong_on_axis_shader
+    for ci, (p, heights, cols, katt, amb, rgb) in enumerate(PHONG_HAND_CASES):
+        sp = phong_on_axis_shader(PERM_MODEL, p, heights, cols, katt, amb)
+        vb = np.array([[*p, 0, 0, 1, 0.25, 0.75]], np.float32)
+        idx = torch.zeros(3 * 5, dtype=torch.int32, device="cuda")
+        vtx = torch.from_numpy(vb).cuda()
+        for strategy, bt in ((vr.VR_NAIVE, 1), (vr.VR_STATIC_HASH, 4)):
+            print(f"[phong hand] case {ci} strategy {vr.STRATEGY_NAMES[strategy]}", flush=True)
+            res = stage.draw(idx, vtx, sp, strategy, bt, corners=True)
+            st, _ = stage.sync()
+            assert st == vr.VR_OK, vr.vr_last_error(stage.ctx)
+            got = res["corners"].cpu().numpy()
+            np.testing.assert_array_equal(got[:, 9:], np.broadcast_to(np.float32(rgb), (15, 3)))
+            np.testing.assert_array_equal(got[:, :4], np.broadcast_to(np.float32([*p, 1.0]), (15, 4)))

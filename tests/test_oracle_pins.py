@@ -357,7 +357,7 @@ def _perm_world(p):
     return np.float32([p[1] + 1.0, p[2] - 2.0, p[0] + 0.5])
 
 
-def _phong_on_axis(model, p, offsets, colours, katt, ambient, kd=0.75, ks=0.25):
+def phong_on_axis_shader(model, p, offsets, colours, katt, ambient, kd=0.75, ks=0.25):
     """Phong with lights at world offsets (0, 0, dz) above the vertex's world
     position w = model (p, 1), the normal +z and the eye at w + (0, 0, 5)."""
     sp = _identity_shader(W.SHADER_PHONG)
@@ -373,7 +373,23 @@ def _phong_on_axis(model, p, offsets, colours, katt, ambient, kd=0.75, ks=0.25):
         lights[l, 3:] = c
     sp.lights = lights
     sp.num_lights = len(offsets)
-    return vro.shade(sp, _vbuf(p))[0]
+    return sp
+
+
+def _phong_on_axis(model, p, *args, **kw):
+    return vro.shade(phong_on_axis_shader(model, p, *args, **kw), _vbuf(p))[0]
+
+
+# (p, light heights, colours, katt, ambient, expected rgb): the hand cases
+# below, also run through the GPU path
+ULP1 = 2.0 ** -23
+PHONG_HAND_CASES = [
+    ((0.5, -1.25, 3.0), [2.0], [(1.0, 0.5, 2.0)], 0.25, (0.25, 0.125, 0.0), (0.75, 0.375, 1.0)),
+    ((0.5, -1.25, 3.0), [1.0, 3.0, 1.0], [(2.0, 0.0, 0.0), (0.0, 4.0, 0.0), (0.0, 0.0, 8.0)], 7.0,
+     (0.0, 0.0, 0.0), (0.25, 0.0625, 1.0)),
+    ((0.5, -1.25, 3.0), [1.0, 2.0], [(0.75 * ULP1, 0.5 * ULP1, 0.0), (0.5 * ULP1, 0.75 * ULP1, 0.0)], 0.0,
+     (1.0, 1.0, 1.0), (1.0 + 2 * ULP1, 1.0 + ULP1, 1.0)),
+]
 
 
 def test_phong_world_position_uses_row_major_model():
