@@ -205,6 +205,36 @@ vr_status vr_process_draw(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_i
                           uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out);
 
 /*
+ * Allocation-free draw, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, and harnesses that
+ * forbid hipMalloc.  Same arguments, outputs, semantics and errors as
+ * vr_process_draw, except:
+ *  - the per-batch aggregates and look-back words live in one static
+ *    device array of the library, 16 bytes per batch for at most
+ *    VR_NOALLOC_MAX_BATCHES batches (8 MiB), which every GPU the library
+ *    runs on holds until the process ends (its address is looked up once
+ *    per device by vr_create);
+ *  - a draw whose batch bound exceeds VR_NOALLOC_MAX_BATCHES is rejected
+ *    with VR_ERR_CAPACITY before anything is enqueued (the bound is
+ *    ceil(T / batch_tris) for static strategies and
+ *    T / min(batch_tris, ceil((N_u - 2) / 3)) + 1 for dynamic ones; NAIVE
+ *    uses no batch scratch);
+ *  - DYN_* need opts->d_plan (built beforehand by vr_plan_dynamic) and
+ *    MULTI needs out->verts (its shaded buffer): VR_ERR_ARG otherwise;
+ *  - kernel timing (vr_set_kernel_timing) records nothing for it.
+ * The call performs no hipMalloc, hipFree or other allocation.  Every call
+ * on a GPU shares that GPU's array and the array keeps the last call's
+ * contents (the look-back words are zero again after every draw): calls
+ * that overlap on one GPU, from any contexts or streams, race and must be
+ * ordered by the caller.  VR_ERR_DEVICE if the array could not be set up.
+ */
+#define VR_NOALLOC_MAX_BATCHES 524288u
+vr_status vr_process_draw_noalloc(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_indices,
+                                  const float *d_vertices, uint32_t num_vertices,
+                                  const vr_shader_params *shader, vr_strategy strategy,
+                                  uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out);
+
+/*
  * Streaming (Sections 4.2 and 5): index chunks are drawn as they arrive with
  * strategies that need no analysis of the index buffer (NAIVE, STATIC_*),
  * each into one of `slots` corner buffers of chunk_tris triangles (owned by

@@ -120,8 +120,8 @@ vr_status ensure(vr_ctx *c, Scratch &s, size_t bytes, bool zero = false) {
 struct TimedRegion {
     vr_ctx *c;
     hipEvent_t stop = nullptr;
-    explicit TimedRegion(vr_ctx *ctx) : c(ctx) {
-        if (!c->timing) return;
+    explicit TimedRegion(vr_ctx *ctx, bool enabled = true) : c(ctx) {
+        if (!c->timing || !enabled) return;
         if (c->ev_used == c->ev_pool.size()) {
             hipEvent_t a = nullptr, b = nullptr;
             if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
@@ -302,6 +302,66 @@ __global__ void k_plan_empty(uint32_t *plan) {
         plan[0] = 0;
         plan[1] = 0;
     }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free draw (vr_process_draw_noalloc): the
+// per-batch aggregates, then the look-back words, of at most
+// VR_NOALLOC_MAX_BATCHES batches.  Every GPU holds its own copy for the life
+// of the process.  In host code `scratch` names a host-side stand-in, never
+// the device memory: the device address comes from hipGetSymbolAddress, once
+// per device (scratch_setup, called by vr_create), and only that address is
+// handed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[16ull * VR_NOALLOC_MAX_BATCHES];
+
+struct ScratchSlot {
+    bool tried = false;
+    unsigned char *ptr = nullptr;   // device address of `scratch` on this device
+    std::string error;
+};
+std::mutex g_scratch_mu;
+std::map<int, ScratchSlot> g_scratch;
+
+// With `device` current: looks up the array's address on it and zeroes its
+// look-back words (a fill kernel, waited for), once per device.  Every draw
+// that uses look-back words clears the ones it used in its k_finish, so they
+// are zero again at the start of the next call.
+void scratch_setup(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchSlot &S = g_scratch[device];
+    if (S.tried) return;
+    S.tried = true;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        S.error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return;
+    }
+    unsigned long long *words = (unsigned long long *)((unsigned char *)p + 8ull * VR_NOALLOC_MAX_BATCHES);
+    hipLaunchKernelGGL(k_fill_u64, dim3(256), dim3(256), 0, nullptr, words, (uint64_t)VR_NOALLOC_MAX_BATCHES, 0ull);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        S.error = std::string("clearing the look-back words: ") + hipGetErrorString(e);
+        return;
+    }
+    S.ptr = (unsigned char *)p;
+}
+
+// The device address of `scratch` on `device`, or NULL (then *why is set).
+unsigned char *scratch_ptr(int device, std::string *why) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(device);
+    if (it == g_scratch.end() || !it->second.ptr) {
+        *why = it == g_scratch.end() ? std::string("not set up") : it->second.error;
+        return nullptr;
+    }
+    return it->second.ptr;
 }
 
 // Builds the plan of a dynamic draw on the context's stream (see vr_plan.h).
@@ -536,6 +596,7 @@ vr_status vr_create(vr_ctx **out, int device, void *hip_stream) {
         delete c;
         return fail(nullptr, VR_ERR_OOM, "context allocation failed");
     }
+    scratch_setup(device);   // a failure is reported by vr_process_draw_noalloc
     *out = c;
     return VR_OK;
 }
@@ -584,9 +645,16 @@ vr_status vr_plan_dynamic(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
     return build_plan(c, d_indices, (uint32_t)T, num_vertices, max_unique, max_tris, d_plan);
 }
 
-vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_indices, const float *d_vertices,
-                          uint32_t num_vertices, const vr_shader_params *shader, vr_strategy strategy,
-                          uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out) {
+}  // extern "C"
+
+namespace {
+
+// One draw (vr_process_draw).  With noalloc the per-batch aggregates and
+// look-back words come from the static `scratch` array instead of context
+// scratch, a dynamic draw must bring its plan, and nothing is allocated.
+vr_status draw_impl(vr_ctx *c, const uint32_t *d_indices, uint64_t num_indices, const float *d_vertices,
+                    uint32_t num_vertices, const vr_shader_params *shader, vr_strategy strategy, uint32_t batch_tris,
+                    const vr_opts *opts, const vr_outputs *out, bool noalloc) {
     if (!c) return VR_ERR_ARG;
     Resolved r;
     vr_status st = check_args(c, num_indices, num_vertices, shader, strategy, batch_tris, opts, out, &r);
@@ -596,6 +664,23 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
     if (d_vertices && ((uintptr_t)d_vertices & 15)) return fail(c, VR_ERR_ARG, "vertices must be 16-byte aligned");
     if (out->corners && ((uintptr_t)out->corners & 15)) return fail(c, VR_ERR_ARG, "corners must be 16-byte aligned");
     if (out->verts && ((uintptr_t)out->verts & 15)) return fail(c, VR_ERR_ARG, "verts must be 16-byte aligned");
+    unsigned char *fixed = nullptr;   // the static scratch array on this device (noalloc)
+    if (noalloc) {
+        if (is_dynamic(strategy) && T && !(opts && opts->d_plan))
+            return fail(c, VR_ERR_ARG, "an allocation-free dynamic draw needs opts->d_plan (vr_plan_dynamic)");
+        if (strategy == VR_MULTI && T && !out->verts)
+            return fail(c, VR_ERR_ARG, "an allocation-free MULTI draw needs out->verts for its shaded buffer");
+        if (!is_dynamic(strategy) && strategy != VR_NAIVE && strategy != VR_MULTI &&
+            (T + batch_tris - 1) / batch_tris > VR_NOALLOC_MAX_BATCHES)
+            return fail(c, VR_ERR_CAPACITY, "%llu batches exceed the allocation-free limit of %u",
+                        (unsigned long long)((T + batch_tris - 1) / batch_tris), (unsigned)VR_NOALLOC_MAX_BATCHES);
+        if (is_dynamic(strategy) && dyn_batch_bound(T, r.nu, batch_tris) > VR_NOALLOC_MAX_BATCHES)
+            return fail(c, VR_ERR_CAPACITY, "up to %llu dynamic batches exceed the allocation-free limit of %u",
+                        (unsigned long long)dyn_batch_bound(T, r.nu, batch_tris), (unsigned)VR_NOALLOC_MAX_BATCHES);
+        std::string why;
+        fixed = scratch_ptr(c->device, &why);
+        if (!fixed) return fail(c, VR_ERR_DEVICE, "allocation-free scratch unavailable: %s", why.c_str());
+    }
     DeviceGuard g(c->device);
     if (T == 0) {
         hipLaunchKernelGGL(k_empty_draw, dim3(1), dim3(64), 0, c->stream, (unsigned long long *)out->counters,
@@ -637,7 +722,7 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
             if (st != VR_OK) return st;
             shaded = (f4 *)c->shaded.ptr;
         }
-        TimedRegion timed(c);
+        TimedRegion timed(c, !noalloc);
         const dim3 gs((num_vertices + 255) / 256), ga((uint32_t)((3ull * T + 255) / 256));
         if (sh.kind == 0) hipLaunchKernelGGL(k_multi_shade<0>, gs, dim3(256), 0, c->stream, A, sh, shaded);
         else if (sh.kind == 1) hipLaunchKernelGGL(k_multi_shade<1>, gs, dim3(256), 0, c->stream, A, sh, shaded);
@@ -647,7 +732,7 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
         return VR_OK;
     }
     if (strategy == VR_NAIVE) {
-        TimedRegion timed(c);
+        TimedRegion timed(c, !noalloc);
         if (sh.kind == 0) launch_naive<0>(c, A, sh);
         else if (sh.kind == 1) launch_naive<1>(c, A, sh);
         else launch_naive<2>(c, A, sh);
@@ -675,19 +760,25 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
     }
     // one workgroup per batch; a dynamic launch covers the batch bound and
     // workgroups past the plan's count return at once
-    st = ensure(c, c->agg, 8ull * nb_bound);
-    if (st != VR_OK) return st;
-    A.agg = (unsigned long long *)c->agg.ptr;
-    if (A.need_prefix) {
-        st = ensure(c, c->status, 8ull * nb_bound, /*zero=*/true);
-        if (st != VR_OK) return st;
-        A.status = (unsigned long long *)c->status.ptr;
+    if (noalloc) {
+        A.agg = (unsigned long long *)fixed;
+        A.status = A.need_prefix ? (unsigned long long *)(fixed + 8ull * VR_NOALLOC_MAX_BATCHES) : nullptr;
         A.status_cap = (uint32_t)nb_bound;
     } else {
-        A.status = nullptr;
-        A.status_cap = (uint32_t)nb_bound;
+        st = ensure(c, c->agg, 8ull * nb_bound);
+        if (st != VR_OK) return st;
+        A.agg = (unsigned long long *)c->agg.ptr;
+        if (A.need_prefix) {
+            st = ensure(c, c->status, 8ull * nb_bound, /*zero=*/true);
+            if (st != VR_OK) return st;
+            A.status = (unsigned long long *)c->status.ptr;
+            A.status_cap = (uint32_t)nb_bound;
+        } else {
+            A.status = nullptr;
+            A.status_cap = (uint32_t)nb_bound;
+        }
     }
-    TimedRegion timed(c);
+    TimedRegion timed(c, !noalloc);
     if (is_ballot(strategy)) {
         const uint32_t lds = align16(ballot_lds_bytes(batch_tris));   // per wavefront
         if (sh.kind == 0) launch_ballot<0>(c, A, sh, lds, nb_bound);
@@ -711,6 +802,25 @@ vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
                        (const unsigned long long *)A.agg, A.status, A.counters, A.total_inv);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vr_status vr_process_draw(vr_ctx *c, const uint32_t *d_indices, uint64_t num_indices, const float *d_vertices,
+                          uint32_t num_vertices, const vr_shader_params *shader, vr_strategy strategy,
+                          uint32_t batch_tris, const vr_opts *opts, const vr_outputs *out) {
+    return draw_impl(c, d_indices, num_indices, d_vertices, num_vertices, shader, strategy, batch_tris, opts, out,
+                     false);
+}
+
+vr_status vr_process_draw_noalloc(vr_ctx *c, const uint32_t *d_indices, uint64_t num_indices,
+                                  const float *d_vertices, uint32_t num_vertices, const vr_shader_params *shader,
+                                  vr_strategy strategy, uint32_t batch_tris, const vr_opts *opts,
+                                  const vr_outputs *out) {
+    return draw_impl(c, d_indices, num_indices, d_vertices, num_vertices, shader, strategy, batch_tris, opts, out,
+                     true);
 }
 
 // ---------------------------------------------------------------------------

@@ -28,6 +28,7 @@ DYNAMIC = (VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH, VR_DYN_BALLOT)
 OUT_FLOATS = 12
 
 EXPORTS = ["vr_create", "vr_destroy", "vr_set_stream", "vr_check_args", "vr_plan_dynamic", "vr_process_draw",
+           "vr_process_draw_noalloc",
            "vr_sync", "vr_walk_step", "vr_stream_create", "vr_stream_push", "vr_stream_finish",
            "vr_stream_destroy", "vr_frame_create", "vr_frame_run", "vr_frame_destroy", "vr_process_draws", "vr_autotune",
            "vr_set_kernel_timing", "vr_kernel_times", "vr_math_selftest", "vr_last_error", "vr_server_create", "vr_server_add_mesh",
@@ -132,6 +133,8 @@ def lib():
         L.vr_process_draw.argtypes = [P, P, C.c_uint64, P, C.c_uint32, C.POINTER(vr_shader_params), C.c_int,
                                       C.c_uint32, C.POINTER(vr_opts), C.POINTER(vr_outputs)]
         L.vr_process_draw.restype = C.c_int
+        L.vr_process_draw_noalloc.argtypes = L.vr_process_draw.argtypes
+        L.vr_process_draw_noalloc.restype = C.c_int
         L.vr_walk_step.argtypes = [P, P, C.c_uint32, P, C.c_uint32, P, P, C.c_uint32, P, C.c_int, C.c_uint32, P, P]
         L.vr_walk_step.restype = C.c_int
         L.vr_stream_create.argtypes = [P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, P, C.c_uint64,
@@ -287,6 +290,16 @@ def vr_process_draw(ctx, indices, vertices, shader, strategy, batch_tris, opts=N
     return lib().vr_process_draw(ctx, _ptr(indices), indices.numel(), _ptr(vertices), V, C.byref(sh),
                                  strategy, batch_tris, C.byref(opts) if opts is not None else None,
                                  C.byref(out))
+
+
+def vr_process_draw_noalloc(ctx, indices, vertices, shader, strategy, batch_tris, opts=None, outputs=None):
+    """As vr_process_draw, with the library's static scratch (no allocation)."""
+    sh = shader if isinstance(shader, vr_shader_params) else make_shader(shader)
+    out = outputs if outputs is not None else vr_outputs()
+    V = vertices.shape[0] if vertices.dim() == 2 else vertices.numel() // 8
+    return lib().vr_process_draw_noalloc(ctx, _ptr(indices), indices.numel(), _ptr(vertices), V, C.byref(sh),
+                                         strategy, batch_tris, C.byref(opts) if opts is not None else None,
+                                         C.byref(out))
 
 
 def vr_sync(ctx):
