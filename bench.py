@@ -5,9 +5,10 @@ triangles), Hilbert order with 5% local swaps in windows of 256, FP32
 attributes, Phong shading with 8 point lights.  One step runs the whole hot
 path once over this draw for every strategy, each producing the per-corner
 shaded output and the invocation count:
-    dynamic batch plan (N_u = 256, N_pmax = 256), shared by the dynamic
+    dynamic batch plan (N_u = 256, N_pmax = 341, the paper's setting, where
+    the unique budget closes most batches), shared by the dynamic
     strategies; naive; static wave64 ballot (64 triangles); dynamic sort,
-    hash and parallel hash (256 / 256).
+    hash and parallel hash (256 / 341).
 value = triangles processed per second over the whole step (all strategies,
 inputs resident in HBM).  Per-strategy throughput and shading rate are
 reported beside it, with the roofline of the dominant kernel and the CPU
@@ -227,11 +228,113 @@ def sweep(mesh, sp, reps=10):
     stage.close()
 
 
-def measure_draw(stage, idx, vtx, V, sp, strategy, bt, nu=0, reps=20, flush=None):
+def unit_chunks(T, cuts, parts):
+    """Split triangles [0, T) into at most `parts` contiguous chunks whose
+    bounds are unit starts (`cuts`, ascending, from 0): each chunk is a draw
+    of its own whose units are exactly the units of the whole draw in it
+    (static batches restart at multiples of the batch size, and greedy
+    dynamic batching restarts at every batch start)."""
+    cuts = np.asarray(cuts, dtype=np.int64)
+    want = [T * k // parts for k in range(1, parts)]
+    pos = np.searchsorted(cuts, want)
+    inner = sorted({int(cuts[p]) for p in pos if p < len(cuts) and 0 < cuts[p] < T})
+    b = [0] + inner + [T]
+    return [(b[i], b[i + 1]) for i in range(len(b) - 1) if b[i + 1] > b[i]]
+
+
+def strategy_cuts(vro, mesh, s, bt, nu):
+    """Unit starts usable as chunk bounds: every triangle (naive), multiples
+    of the batch size (static), the dynamic plan's batch starts (dynamic)."""
+    from paper_1805_08893_amd import vr
+    T = mesh.num_tris
+    if s == vr.VR_NAIVE:
+        return np.arange(T, dtype=np.int64)
+    if s in vr.DYNAMIC:
+        assert nu >= 3, "dynamic strategies name their unique budget"
+        return vro.plan_dynamic(mesh.indices, mesh.num_verts, nu, bt)[:-1]
+    return np.arange(0, T, bt, dtype=np.int64)
+
+
+def cpu_oracle_baseline(mesh, sp, strategies, st_passes, mt_passes):
+    """The C oracle timed on the host: (i) one thread over whole draws, and
+    (ii) all host threads, each running the oracle on a contiguous chunk of
+    whole units (the dynamic plan is made first, sequentially, and timed
+    apart; each chunk then plans its own part again, inside the parallel
+    time).  The chunks' invocation counts must add up to the whole draw's.
+    Beside it, the k-entry FIFO post-transform cache (k = 16, 32) as the
+    classic comparison point for the invocations of each strategy."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import vro
+    T, V = mesh.num_tris, mesh.num_verts
+    U = int(len(np.unique(mesh.indices)))
+    threads = len(os.sched_getaffinity(0))
+    vsh = vro.make_shader(sp)
+    whole = {}
+    t_st, tris_st = 0.0, 0
+    for _ in range(st_passes):
+        for name, s, bt, nu in strategies:
+            c0 = time.perf_counter()
+            rc, r = vro.process_draw(mesh.indices, mesh.vertices, vsh, s, bt, {"max_unique": nu}, tris=False,
+                                     verts=False, local_idx=False, units=False)
+            t_st += time.perf_counter() - c0
+            tris_st += T
+            assert rc == vro.OK, (name, rc)
+            whole[name] = int(r["counters"][0])
+    # plans (sequential), then the chunks of every strategy on all threads
+    plan_s, chunks = {}, {}
+    for name, s, bt, nu in strategies:
+        c0 = time.perf_counter()
+        cuts = strategy_cuts(vro, mesh, s, bt, nu)
+        plan_s[name] = time.perf_counter() - c0
+        chunks[name] = unit_chunks(T, cuts, threads)
+
+    def run(name, s, bt, nu, a, b):
+        rc, r = vro.process_draw(mesh.indices[3 * a:3 * b], mesh.vertices, vsh, s, bt, {"max_unique": nu},
+                                 tris=False, verts=False, local_idx=False, units=False)
+        assert rc == vro.OK, (name, rc)
+        return int(r["counters"][0])
+
+    t_mt, tris_mt, per = 0.0, 0, {}
+    with ThreadPoolExecutor(threads) as pool:
+        for _ in range(mt_passes):
+            for name, s, bt, nu in strategies:
+                c0 = time.perf_counter()
+                inv = sum(pool.map(lambda ab: run(name, s, bt, nu, *ab), chunks[name]))
+                dt = time.perf_counter() - c0
+                t_mt += dt
+                tris_mt += T
+                per[name] = per.get(name, 0.0) + dt
+                if inv != whole[name]:
+                    raise RuntimeError(f"{name}: chunked oracle invocations {inv} != whole draw {whole[name]}")
+    fifo = {}
+    for k in (16, 32):
+        m = vro.fifo_misses(mesh.indices, V, k)
+        fifo[f"fifo{k}"] = {"invocations": m, "shading_rate": m / U, "reuse": 1.0 - m / (3.0 * T)}
+    from paper_1805_08893_amd import vr
+    plan_total = sum(plan_s[n] for n, s, *_ in strategies if s in vr.DYNAMIC)
+    return {"value": tris_mt / t_mt, "unit": "triangles/s", "cores": threads, "kind": "oracle",
+            "sample": f"{mt_passes} pass(es) of the full step ({len(strategies)} draws x {T} triangles) on "
+                      f"{threads} threads, each thread the C oracle on a contiguous chunk of whole units, "
+                      f"{t_mt:.1f} s wall; dynamic plans made beforehand on one thread ({plan_total:.2f} s, "
+                      f"not in the value)",
+            "single_thread": {"value": tris_st / t_st, "cores": 1,
+                              "sample": f"{st_passes} pass(es) of the full step, one thread, {t_st:.1f} s"},
+            "per_strategy_ms_all_cores": {n: 1e3 * v / mt_passes for n, v in per.items()},
+            "plan_ms_one_thread": {n: 1e3 * plan_s[n] for n, s, *_ in strategies if s in vr.DYNAMIC},
+            "fifo_post_transform_cache": fifo,
+            "host_cpu": host_cpu_model(), "host_threads": threads}
+
+
+
+def measure_draw(stage, idx, vtx, V, sp, strategy, bt, nu=0, reps=20, flush=None, output="corners", U=None):
     """One configuration: plan time (dynamic), main-kernel time from the
     library's HIP events, draw time (events around the whole call) p50/p99,
-    invocations and the roofline fractions.  With `flush` (a device tensor)
-    the caches are overwritten before every timed draw (cold runs)."""
+    invocations and the roofline fractions.  output = "corners" (per-corner
+    shaded vertices, 144 B per triangle) or "indexed" (the shaded vertices of
+    every unit once plus the assembled index triangles: 48 B per invocation
+    and 12 B per triangle).  U = distinct indices of the draw (default V).
+    With `flush` (a device tensor) the caches are overwritten before every
+    timed draw (cold runs)."""
     import torch
     from paper_1805_08893_amd import vr
     T = idx.numel() // 3
@@ -246,7 +349,8 @@ def measure_draw(stage, idx, vtx, V, sp, strategy, bt, nu=0, reps=20, flush=None
             stage.check(vr.vr_plan_dynamic(stage.ctx, idx, V, nu, bt, plan))
         plan_ms = float(np.median(vr.vr_kernel_times(stage.ctx)))
         vr.vr_set_kernel_timing(stage.ctx, False)
-    out = stage.alloc_outputs(T, strategy, bt, corners=True, num_vertices=V)
+    indexed = output == "indexed"
+    out = stage.alloc_outputs(T, strategy, bt, corners=not indexed, tris=indexed, verts=indexed, num_vertices=V)
     o = vr.make_opts(max_unique=nu, plan=plan)
     for _ in range(3):
         stage.check(vr.vr_process_draw(stage.ctx, idx, vtx, sh, strategy, bt, o, stage.describe(out)))
@@ -268,16 +372,80 @@ def measure_draw(stage, idx, vtx, V, sp, strategy, bt, nu=0, reps=20, flush=None
     stage.check(st)
     ms = np.array([a.elapsed_time(b) for a, b in ev])
     inv = int(out["counters"][0].item())
-    U = int(V)
+    units = int(out["counters"][1].item())
+    U = int(V) if U is None else int(U)
     k = float(np.median(kms))
-    alg = 12 * T + 32 * min(U, inv) + 144 * T
-    if strategy == vr.VR_MULTI:   # the shaded buffer is written once and read back at least once
-        alg = 12 * T + 32 * U + 96 * U + 144 * T
-    return {"batch_tris": bt, "max_unique": nu, "kernel_ms_p50": k, "draw_ms_p50": float(np.percentile(ms, 50)),
-            "draw_ms_p99": float(np.percentile(ms, 99)), "plan_ms_p50": plan_ms, "invocations": inv,
+    alg = algorithmic_bytes(T, U, inv, output, multi=strategy == vr.VR_MULTI)
+    return {"output": output, "batch_tris": bt, "max_unique": nu, "kernel_ms_p50": k,
+            "draw_ms_p50": float(np.percentile(ms, 50)), "draw_ms_p99": float(np.percentile(ms, 99)),
+            "plan_ms_p50": plan_ms, "invocations": inv, "units": units, "shading_rate": inv / U,
             "reuse": 1.0 - inv / (3.0 * T), "tri_per_s": T / (k * 1e-3),
+            "tri_per_s_with_plan": T / ((k + (plan_ms or 0.0)) * 1e-3), "algorithmic_bytes": alg,
             "hbm_frac": alg / (k * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "alu_frac": inv * shader_flops(sp) / (k * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS}
+
+
+def algorithmic_bytes(T, U, inv, output="corners", multi=False):
+    """Bytes a draw must move at least: its indices (12 B per triangle),
+    every referenced vertex once (32 B), and its outputs: 144 B per triangle
+    of per-corner vertices, or 48 B per invocation of shaded vertices plus
+    12 B per triangle of assembled indices.  The two-pass reference also
+    writes its shaded buffer (48 B per vertex) and reads it back once."""
+    if multi:   # indexed: the shaded buffer is the output
+        return 12 * T + 32 * U + (96 * U + 144 * T if output == "corners" else 48 * U + 12 * T)
+    base = 12 * T + 32 * min(U, inv)
+    return base + (144 * T if output == "corners" else 48 * inv + 12 * T)
+
+
+def batch_sweep(stage, idx, vtx, V, U, sp, reps=10):
+    """The bench workload over batch sizes {32, 64, 128, 256}: static ballot,
+    sort and hash with N_p = B, and the dynamic strategies with N_pmax = B and
+    N_u = 64 ceil(B / 64); then the paper's point (N_u 256, N_pmax 341) and
+    the shading rate against the unique budget N_u with N_pmax = 4 N_u / 3
+    (dynamic hash).  Main-kernel time, plan time, invocations, shading rate."""
+    from paper_1805_08893_amd import vr
+    rows = []
+
+    def add(name, s, bt, nu):
+        r = measure_draw(stage, idx, vtx, V, sp, s, bt, nu, reps=reps, U=U)
+        rows.append({"strategy": name, "batch_tris": bt, "max_unique": nu,
+                     "kernel_us": round(r["kernel_ms_p50"] * 1e3, 1),
+                     "plan_us": None if r["plan_ms_p50"] is None else round(r["plan_ms_p50"] * 1e3, 1),
+                     "invocations": r["invocations"], "shading_rate": round(r["shading_rate"], 4),
+                     "tri_per_s": r["tri_per_s"], "hbm_frac": round(r["hbm_frac"], 4)})
+
+    for B in (32, 64, 128, 256):
+        nu = 64 * -(-B // 64)
+        for name, s in (("static_ballot", vr.VR_STATIC_BALLOT), ("static_sort", vr.VR_STATIC_SORT),
+                        ("static_hash", vr.VR_STATIC_HASH)):
+            add(name, s, B, 0)
+        for name, s in (("dyn_ballot", vr.VR_DYN_BALLOT), ("dyn_sort", vr.VR_DYN_SORT),
+                        ("dyn_hash", vr.VR_DYN_HASH), ("dyn_phash", vr.VR_DYN_PHASH)):
+            add(name, s, B, nu)
+    for name, s in (("dyn_sort", vr.VR_DYN_SORT), ("dyn_hash", vr.VR_DYN_HASH), ("dyn_phash", vr.VR_DYN_PHASH)):
+        add(name, s, 341, 256)
+    curve = []
+    for nu in (64, 128, 256, 384, vr.VR_MAX_UNIQUE):
+        bt = min(vr.VR_MAX_BATCH_DYNAMIC, 4 * nu // 3)
+        r = measure_draw(stage, idx, vtx, V, sp, vr.VR_DYN_HASH, bt, nu, reps=reps, U=U)
+        curve.append({"max_unique": nu, "batch_tris": bt, "shading_rate": round(r["shading_rate"], 4),
+                      "kernel_us": round(r["kernel_ms_p50"] * 1e3, 1),
+                      "plan_us": round(r["plan_ms_p50"] * 1e3, 1)})
+    return {"rows": rows, "shading_rate_vs_max_unique": curve}
+
+
+def indexed_outputs(stage, idx, vtx, V, U, sp, configs, reps=10):
+    """Each strategy with the indexed outputs (the shaded vertices of every
+    unit once and the assembled index triangles), where reuse cuts the bytes
+    written, against the per-corner form."""
+    out = {}
+    for name, s, bt, nu in configs:
+        out[name] = measure_draw(stage, idx, vtx, V, sp, s, bt, nu, reps=reps, output="indexed", U=U)
+    naive = out.get("naive")
+    if naive:
+        for r in out.values():
+            r["speedup_vs_naive"] = naive["kernel_ms_p50"] / r["kernel_ms_p50"]
+    return out
 
 
 def plain_latency(stage, reps=50):
@@ -311,7 +479,7 @@ def heavy_orders(stage, reps=10):
     """The heavy shader on a large grid (2048 x 2048 vertices, 8,380,418
     triangles, normal offset with 64 iterations) in Hilbert and in fully
     random triangle order: naive, dynamic ballot (N_u 64 / N_pmax 85) and
-    dynamic hash (256 / 341)."""
+    dynamic hash (256 / 341), with per-corner and with indexed outputs."""
     import torch
     from paper_1805_08893_amd import vr
     from paper_1805_08893_amd import workloads as W
@@ -320,9 +488,13 @@ def heavy_orders(stage, reps=10):
         mesh, sp = W.grid2048_offset64(order)
         idx = torch.from_numpy(mesh.indices.view(np.int32)).cuda()
         vtx = torch.from_numpy(mesh.vertices).cuda()
+        cfgs = (("naive", vr.VR_NAIVE, 1, 0), ("dyn_ballot", vr.VR_DYN_BALLOT, 85, 64),
+                ("dyn_hash", vr.VR_DYN_HASH, 341, 256))
         out[order] = {name: measure_draw(stage, idx, vtx, mesh.num_verts, sp, s, bt, nu, reps=reps)
-                      for name, s, bt, nu in (("naive", vr.VR_NAIVE, 1, 0), ("dyn_ballot", vr.VR_DYN_BALLOT, 85, 64),
-                                              ("dyn_hash", vr.VR_DYN_HASH, 341, 256))}
+                      for name, s, bt, nu in cfgs}
+        out[order]["indexed"] = {name: measure_draw(stage, idx, vtx, mesh.num_verts, sp, s, bt, nu, reps=reps,
+                                                    output="indexed")
+                                 for name, s, bt, nu in cfgs}
         del idx, vtx
         torch.cuda.empty_cache()
         progress(f"heavy {order} done")
@@ -511,7 +683,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-passes", type=int, default=6, help="passes of the full step the CPU oracle times (about 10 s)")
+    ap.add_argument("--cpu-passes", type=int, default=3,
+                    help="passes of the full step the one-thread CPU oracle times (about 5 s)")
+    ap.add_argument("--cpu-mt-passes", type=int, default=12,
+                    help="passes of the full step the all-threads CPU oracle times")
     ap.add_argument("--level", type=int, default=8, help="icosphere subdivision level")
     ap.add_argument("--only", default=None, help="run only this strategy in each step (profiling)")
     ap.add_argument("--no-scene", action="store_true", help="skip the many-draw frame measurement")
@@ -562,7 +737,7 @@ def main():
     vtx = torch.from_numpy(mesh.vertices).cuda()
     stage = vr.GeometryStage(0)
     plan = torch.empty(T + 2, dtype=torch.int32, device="cuda")
-    NU, NP = 256, 256
+    NU, NP = 256, 341   # the paper's dynamic setting: N_u = 256 binds before N_pmax = 341
     strategies = [("naive", vr.VR_NAIVE, 1, {}),
                   ("static_ballot", vr.VR_STATIC_BALLOT, 64, {}),
                   ("dyn_sort", vr.VR_DYN_SORT, NP, dict(max_unique=NU, plan=plan)),
@@ -661,20 +836,9 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        from oracle import vro
-        t_cpu, tris_cpu = 0.0, 0
-        for _ in range(args.cpu_passes):
-            for name, s, bt, o in strategies:
-                c0 = time.perf_counter()
-                rc, _ = vro.process_draw(mesh.indices, mesh.vertices, sp, s, bt,
-                                         {"max_unique": o.get("max_unique", 0)}, tris=False, verts=False,
-                                         local_idx=False, units=False)
-                t_cpu += time.perf_counter() - c0
-                tris_cpu += T
-        cpu = {"value": tris_cpu / t_cpu, "unit": "triangles/s", "cores": 1, "kind": "oracle",
-               "sample": f"{args.cpu_passes} pass(es) of the full step (5 strategies x {T} triangles), "
-                         f"single-threaded C oracle, {t_cpu:.1f} s",
-               "host_cpu": host_cpu_model(), "host_threads": len(os.sched_getaffinity(0))}
+        cpu = cpu_oracle_baseline(mesh, sp, [(n, s, bt, o.get("max_unique", 0)) for n, s, bt, o in strategies],
+                                  args.cpu_passes, args.cpu_mt_passes)
+        progress("CPU oracle done")
 
     cold = None
     if not args.only and not args.no_extra:
@@ -685,6 +849,18 @@ def main():
         del flush
         torch.cuda.empty_cache()
         progress("cold runs done")
+    indexed = sweep_rows = None
+    if not args.only and not args.no_extra:
+        try:
+            indexed = indexed_outputs(stage, idx, vtx, V, U, sp,
+                                      [("naive", vr.VR_NAIVE, 1, 0), ("static_ballot", vr.VR_STATIC_BALLOT, 64, 0),
+                                       ("dyn_ballot", vr.VR_DYN_BALLOT, 85, 64), ("dyn_sort", vr.VR_DYN_SORT, NP, NU),
+                                       ("dyn_hash", vr.VR_DYN_HASH, NP, NU), ("dyn_phash", vr.VR_DYN_PHASH, NP, NU)])
+            progress("indexed outputs done")
+            sweep_rows = batch_sweep(stage, idx, vtx, V, U, sp)
+            progress("batch sweep done")
+        except Exception as exc:   # the headline line must still be printed
+            indexed = {"error": repr(exc)}
     multi = None
     if not args.only and not args.no_extra:
         # the two-pass reference (shade the vertex buffer, then gather)
@@ -734,7 +910,8 @@ def main():
                        "unique_vertices": U, "strategies": [s[0] for s in strategies],
                        "static_batch_tris": 64, "dynamic_max_unique": NU, "dynamic_max_tris": NP,
                        "output": "per-corner shaded vertices + invocation counters"},
-            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "multi": multi, "cold": cold, "plain": plain, "heavy": heavy, "stream": stream, "walk": walk, "scene": scene,
+            "roofline": roof, "cpu_baseline": cpu, "per_strategy": per, "indexed": indexed, "sweep": sweep_rows,
+            "multi": multi, "cold": cold, "plain": plain, "heavy": heavy, "stream": stream, "walk": walk, "scene": scene,
             "serving": serving}
     print(json.dumps(line), flush=True)
     stage.close()

@@ -40,3 +40,32 @@ def test_kernel_source_hash_is_stable():
 def test_host_cpu_model_is_text_or_none():
     m = bench.host_cpu_model()
     assert m is None or (isinstance(m, str) and m)
+
+
+def test_unit_chunks_cut_only_at_unit_starts():
+    cuts = [0, 5, 9, 30, 31, 60]
+    ch = bench.unit_chunks(70, cuts, 4)
+    assert ch[0][0] == 0 and ch[-1][1] == 70
+    assert all(a < b for a, b in ch)
+    assert all(ch[i][1] == ch[i + 1][0] for i in range(len(ch) - 1))
+    assert {b for _, b in ch[:-1]} <= set(cuts)
+    assert bench.unit_chunks(10, [0], 8) == [(0, 10)]
+
+
+def test_all_threads_oracle_leg_adds_up_to_the_whole_draws():
+    # every strategy family on a small icosphere: the chunked runs must give
+    # the whole draw's invocations (checked inside the leg), and the FIFO
+    # comparison point lies between the unique count and 3T
+    from paper_1805_08893_amd import vr
+    mesh = W.icosphere_mesh(4, 2, "hilbert", swap_frac=0.05)
+    sp = W.shader_for_mesh(mesh, W.SHADER_PHONG, 2, num_lights=2)
+    strategies = [("naive", vr.VR_NAIVE, 1, 0), ("static_ballot", vr.VR_STATIC_BALLOT, 64, 0),
+                  ("static_sort", vr.VR_STATIC_SORT, 64, 0), ("dyn_hash", vr.VR_DYN_HASH, 341, 256),
+                  ("dyn_ballot", vr.VR_DYN_BALLOT, 85, 64)]
+    r = bench.cpu_oracle_baseline(mesh, sp, strategies, 1, 1)
+    assert r["cores"] >= 1 and r["value"] > 0 and r["single_thread"]["cores"] == 1
+    U = len(set(mesh.indices.tolist()))
+    for k in ("fifo16", "fifo32"):
+        m = r["fifo_post_transform_cache"][k]["invocations"]
+        assert U <= m <= 3 * mesh.num_tris
+    assert set(r["plan_ms_one_thread"]) == {"dyn_hash", "dyn_ballot"}
