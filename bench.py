@@ -425,12 +425,16 @@ def batch_sweep(stage, idx, vtx, V, U, sp, reps=10):
     for name, s in (("dyn_sort", vr.VR_DYN_SORT), ("dyn_hash", vr.VR_DYN_HASH), ("dyn_phash", vr.VR_DYN_PHASH)):
         add(name, s, 341, 256)
     curve = []
-    for nu in (64, 128, 256, 384, vr.VR_MAX_UNIQUE):
-        bt = min(vr.VR_MAX_BATCH_DYNAMIC, 4 * nu // 3)
-        r = measure_draw(stage, idx, vtx, V, sp, vr.VR_DYN_HASH, bt, nu, reps=reps, U=U)
-        curve.append({"max_unique": nu, "batch_tris": bt, "shading_rate": round(r["shading_rate"], 4),
-                      "kernel_us": round(r["kernel_ms_p50"] * 1e3, 1),
-                      "plan_us": round(r["plan_ms_p50"] * 1e3, 1)})
+    # per-corner outputs keep every unique vertex of a unit in LDS (48 B
+    # each): up to N_u = 2048; indexed outputs stream them out: up to 4096
+    for output, budgets in (("corners", (64, 128, 256, 512, 1024, 2048)), ("indexed", (1024, 2048, 3072, 4096))):
+        for nu in budgets:
+            bt = min(vr.VR_MAX_BATCH_DYNAMIC, 4 * nu // 3)
+            r = measure_draw(stage, idx, vtx, V, sp, vr.VR_DYN_HASH, bt, nu, reps=reps, U=U, output=output)
+            curve.append({"output": output, "max_unique": nu, "batch_tris": bt,
+                          "shading_rate": round(r["shading_rate"], 4), "kernel_us": round(r["kernel_ms_p50"] * 1e3, 1),
+                          "plan_us": round(r["plan_ms_p50"] * 1e3, 1), "tri_per_s": r["tri_per_s"],
+                          "hbm_frac": round(r["hbm_frac"], 4)})
     return {"rows": rows, "shading_rate_vs_max_unique": curve}
 
 
@@ -577,6 +581,45 @@ def stream_benchmark(stage, idx, vtx, sp, T, chunk=65536, reps=5):
     return out
 
 
+def plan_probe(reps=20):
+    """The dynamic planner alone (vr_plan_dynamic), timed by HIP events on the
+    large icosphere (1,310,720 triangles) and the large grid (8,380,418
+    triangles, Hilbert and random order) at the budgets the draws use."""
+    import torch
+    from paper_1805_08893_amd import vr
+    from paper_1805_08893_amd import workloads as W
+    stage = vr.GeometryStage(0)
+    out = {}
+    cases = [("icosphere8", None, [(256, 341), (256, 256), (64, 85), (1024, 1365), (4096, 4096)]),
+             ("grid2048_hilbert", "hilbert", [(64, 85), (256, 341)]),
+             ("grid2048_random", "random", [(256, 341), (64, 85), (2048, 2730)])]
+    for name, order, budgets in cases:
+        mesh = W.icosphere8_hilbert_phong8()[0] if order is None else W.grid2048_offset64(order)[0]
+        idx = torch.from_numpy(mesh.indices.view(np.int32)).cuda()
+        plan = torch.empty(mesh.num_tris + 2, dtype=torch.int32, device="cuda")
+        for nu, npm in budgets:
+            def run():
+                stage.check(vr.vr_plan_dynamic(stage.ctx, idx, mesh.num_verts, nu, npm, plan))
+            run()
+            ms = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                run()
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            st, _ = stage.sync()
+            stage.check(st)
+            out[f"{name}_{nu}_{npm}"] = {"ms_p50": float(np.median(ms)), "batches": int(plan[0].item()),
+                                         "triangles": mesh.num_tris}
+            progress(f"plan probe {name} {nu}/{npm}: {np.median(ms):.4f} ms")
+        del idx, plan
+        torch.cuda.empty_cache()
+    stage.close()
+    return out
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -695,6 +738,8 @@ def main():
                     help="skip the cold-cache runs, the small-grid latency and the heavy-shader orders")
     ap.add_argument("--sweep", action="store_true",
                     help="time every strategy over batch sizes 32..1024 on the workload and exit")
+    ap.add_argument("--plan-probe", action="store_true",
+                    help="time the dynamic planner alone on the large icosphere and the large grid and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="time a plain device-to-device copy of BYTES (counter calibration) and exit")
     args = ap.parse_args()
@@ -726,6 +771,9 @@ def main():
             moved = (2 if name == "copy" else 1) * args.copy_probe
             out[name] = {"ms": ms, "GBps": moved / (ms * 1e-3) / 1e9}
         print(json.dumps(out), flush=True)
+        return
+    if args.plan_probe:
+        print(json.dumps(plan_probe(reps=max(3, min(args.steps, 50)))), flush=True)
         return
     mesh, sp = W.icosphere8_hilbert_phong8(level=args.level)
     T, V = mesh.num_tris, mesh.num_verts
@@ -855,7 +903,9 @@ def main():
             indexed = indexed_outputs(stage, idx, vtx, V, U, sp,
                                       [("naive", vr.VR_NAIVE, 1, 0), ("static_ballot", vr.VR_STATIC_BALLOT, 64, 0),
                                        ("dyn_ballot", vr.VR_DYN_BALLOT, 85, 64), ("dyn_sort", vr.VR_DYN_SORT, NP, NU),
-                                       ("dyn_hash", vr.VR_DYN_HASH, NP, NU), ("dyn_phash", vr.VR_DYN_PHASH, NP, NU)])
+                                       ("dyn_hash", vr.VR_DYN_HASH, NP, NU), ("dyn_phash", vr.VR_DYN_PHASH, NP, NU),
+                                       ("dyn_hash_4096", vr.VR_DYN_HASH, 4096, 4096),
+                                       ("dyn_phash_4096", vr.VR_DYN_PHASH, 4096, 4096)])
             progress("indexed outputs done")
             sweep_rows = batch_sweep(stage, idx, vtx, V, U, sp)
             progress("batch sweep done")

@@ -97,21 +97,28 @@ typedef enum {
     VR_MULTI = 8
 } vr_strategy;
 
-/* Limits on batch_tris per strategy (argument error beyond them). */
+/* Limits on batch_tris per strategy (argument error beyond them).  A DYN_*
+ * sort, hash or parallel-hash draw must also fit one workgroup: at most
+ * 1024 threads (a unit of at most 8 indices per thread for the sort, 32 for
+ * the hashes) and the device's LDS per workgroup (160 KB on gfx950), which
+ * holds 48 bytes per unique vertex when corners are requested and an
+ * NT-row stage otherwise; vr_process_draw returns VR_ERR_ARG before any
+ * launch for a configuration that does not fit. */
 #define VR_MAX_BATCH_STATIC 256        /* STATIC_SORT, STATIC_HASH            */
 #define VR_MAX_BATCH_BALLOT 1024       /* STATIC_BALLOT                       */
-#define VR_MAX_BATCH_DYNAMIC 512       /* DYN_* (the triangle cap N_pmax)     */
-#define VR_MAX_UNIQUE 512              /* DYN_* unique budget N_u             */
+#define VR_MAX_BATCH_DYNAMIC 4096      /* DYN_* (the triangle cap N_pmax)     */
+#define VR_MAX_UNIQUE 4096             /* DYN_* unique budget N_u             */
+#define VR_MAX_HASH_SLOTS 8192         /* opts.hash_slots                     */
 #define VR_MAX_INDICES 3221225469ull   /* num_indices < 3 * 2^30              */
 #define VR_MAX_LIGHTS 16
 
 typedef struct {
     uint32_t max_unique;   /* N_u for DYN_*: 0 = 64*ceil(batch_tris/64) capped
-                              at 512, else 3..512.  Ignored by static modes.   */
+                              at 4096, else 3..4096.  Ignored by static modes. */
     uint32_t wg_size;      /* 0 = automatic, else a multiple of 64 <= 1024;
                               changes launch shape only, never results.        */
     uint32_t hash_slots;   /* 0 = automatic, else a power of two >= the unit's
-                              distinct bound (N_u, or 3*batch_tris) and <= 4096;
+                              distinct bound (N_u, or 3*batch_tris) and <= 8192;
                               never changes results.                            */
     uint32_t hash_probes;  /* DYN_PHASH per-lane probes before the cooperative
                               path: 0 = 4, else <= 64; never changes results.   */
@@ -185,7 +192,7 @@ vr_status vr_check_args(uint64_t num_indices, uint32_t num_vertices,
  * indices or max_tris triangles.  Runs on the device.  Writes into d_plan
  * (uint32[T+2], caller-owned): d_plan[0] = B, d_plan[1..B+1] = the batch
  * start triangles followed by T.  plan_cap is the length of d_plan in
- * elements and must be >= T+2.  max_unique in 3..512, max_tris in 1..512.
+ * elements and must be >= T+2.  max_unique in 3..4096, max_tris in 1..4096.
  */
 vr_status vr_plan_dynamic(vr_ctx *ctx, const uint32_t *d_indices, uint64_t num_indices,
                           uint32_t num_vertices, uint32_t max_unique, uint32_t max_tris,
@@ -326,8 +333,10 @@ typedef struct {
  * valid while the frame exists).  With capture_graph != 0 the frame's
  * launches are captured once into a hipGraph that vr_frame_run replays.
  * Returns VR_ERR_ARG for more than VR_MAX_FRAME_DRAWS draws, a shader index
- * out of range, a dynamic draw without a plan, or any per-draw argument error
- * (vr_last_error names the draw). */
+ * out of range, a dynamic draw without a plan, a sort draw of more than 682
+ * or a hash draw of more than 2730 triangles per batch (the frame kernel runs
+ * 256 threads per unit), or any per-draw argument error (vr_last_error names
+ * the draw). */
 vr_status vr_frame_create(vr_ctx *ctx, const vr_draw *draws, uint32_t num_draws, const vr_shader_params *shaders,
                           uint32_t num_shaders, int capture_graph, vr_frame **frame);
 /* Enqueue the frame on its context's stream (a graph launch when captured). */

@@ -49,7 +49,7 @@ static uint32_t max_batch_tris(int s)
     case VRO_STATIC_BALLOT: return 1024;
     case VRO_STATIC_SORT:
     case VRO_STATIC_HASH: return 256;
-    default: return 512;
+    default: return 4096;
     }
 }
 
@@ -82,15 +82,15 @@ int vro_check_args(uint64_t num_indices, uint32_t num_vertices, const vro_shader
     if (is_dynamic(strategy)) {
         if (nu == 0) {
             nu = 64u * ((batch_tris + 63u) / 64u);
-            if (nu > 512) nu = 512;
+            if (nu > 4096) nu = 4096;
         }
-        if (nu < 3 || nu > 512) return VRO_ERR_ARG;
+        if (nu < 3 || nu > 4096) return VRO_ERR_ARG;
     } else {
         nu = 0;
     }
     if (slots != 0) {
         uint32_t need = is_dynamic(strategy) ? nu : 3u * batch_tris;
-        if ((slots & (slots - 1)) != 0 || slots < need || slots > 4096) return VRO_ERR_ARG;
+        if ((slots & (slots - 1)) != 0 || slots < need || slots > 8192) return VRO_ERR_ARG;
     }
     uint64_t T = num_indices / 3;
     if (out->verts && out->verts_cap < (strategy == VRO_MULTI ? (uint64_t)num_vertices : 3 * T))

@@ -323,11 +323,15 @@ constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagInc = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
 
+// The status words carry their whole payload, so they need no ordering
+// with other memory: relaxed atomics at agent scope (coherent across the
+// XCDs' L2s) suffice, and no release or acquire fence writes back or
+// invalidates the L2.
 __device__ __forceinline__ void status_store(unsigned long long *p, uint64_t v) {
-    __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t status_load(unsigned long long *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Publishes unit b's aggregate; called by one thread.
@@ -335,33 +339,43 @@ __device__ __forceinline__ void lookback_publish(unsigned long long *status, uin
     status_store(&status[b], (b == 0 ? kFlagInc : kFlagAgg) | agg);
 }
 
-// Returns the exclusive prefix of unit b (packed), called by one thread
-// after lookback_publish.  Unit b is workgroup b.  Workgroups are dispatched
-// in index order within each XCD (the grid is dealt round-robin over the
-// XCDs), so when b runs, the lowest unfinished unit has been dispatched or
-// its XCD holds only lower, finishing units: every wait ends.  A bounded
-// spin still turns a lost update into an error instead of a hang.
+// Returns the exclusive prefix of unit b (packed), called by every lane of
+// one wavefront after lookback_publish.  The wavefront reads the status
+// words of the 64 preceding units at once; when every unit down to the
+// nearest inclusive prefix is ready, it adds their values, otherwise it
+// reads the same window again.  Unit b is workgroup b.  Workgroups are
+// dispatched in index order within each XCD (the grid is dealt round-robin
+// over the XCDs), so when b runs, the lowest unfinished unit has been
+// dispatched or its XCD holds only lower, finishing units: every wait ends.
+// A bounded spin still turns a lost update into an error instead of a hang.
 __device__ __forceinline__ uint64_t lookback_resolve(unsigned long long *status, uint32_t b, uint64_t agg,
                                                      uint32_t *err) {
-    if (b == 0) return 0;
+    const uint32_t lane = lane_id();
     uint64_t excl = 0;
-    int64_t j = (int64_t)b - 1;
+    int64_t hi = (int64_t)b;   // the window is units hi - 64 .. hi - 1, lane i reading hi - 1 - i
     uint32_t spins = 0;
-    while (j >= 0) {
-        uint64_t s = status_load(&status[j]);
-        if ((s >> 62) == 0) {
+    while (hi > 0) {
+        const int64_t j = hi - 1 - (int64_t)lane;
+        const uint64_t s = j >= 0 ? status_load(&status[j]) : kFlagInc;   // before unit 0: an empty prefix
+        const uint64_t inc = ballot((s >> 62) == 2);
+        // lanes up to and including the nearest inclusive prefix (all 64 when none)
+        const uint64_t need = inc ? ((inc & (~inc + 1)) << 1) - 1 : ~0ull;
+        if (ballot((s >> 62) == 0) & need) {
             if (++spins > (1u << 26)) {
-                raise_error(err, VR_ERR_DEVICE);
+                if (lane == 0) raise_error(err, VR_ERR_DEVICE);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        excl += s & kValMask;
-        if (s & kFlagInc) break;
-        --j;
+        const bool take = (need >> lane) & 1ull;
+        const uint32_t lo = take ? (uint32_t)s : 0u, up = take ? (uint32_t)((s & kValMask) >> 32) : 0u;
+        excl += ((uint64_t)__builtin_amdgcn_readlane(wave_incl_scan(up), kWave - 1) << 32) |
+                __builtin_amdgcn_readlane(wave_incl_scan(lo), kWave - 1);
+        if (inc) break;
+        hi -= kWave;
     }
-    status_store(&status[b], kFlagInc | (excl + agg));
+    if (lane == 0) status_store(&status[b], kFlagInc | (excl + agg));
     return excl;
 }
 

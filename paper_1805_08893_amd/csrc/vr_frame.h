@@ -1,16 +1,19 @@
-// Many draws in one persistent launch (a frame).
+// Many draws in one persistent launch per variant (a frame).
 //
 // The streaming pipeline of the paper processes the index buffer batch by
 // batch (Sections 3 and 4.2); a frame applies that to a list of draws of
 // uneven size at once.  Every draw keeps exactly the units the single-draw
 // path computes: static batches, dynamic batches from its plan, ballot
-// batches (one wavefront each) or naive chunks of 256 corners.  A prepare
-// kernel counts each draw's units and prefix-sums them into one unit space;
-// the persistent kernel deals that space out to its workgroups in chunks of
-// kFrameChunk units, round robin, finds each unit's draw by binary search in
-// an LDS copy of the draw bases, and dispatches on the draw's dedup mode and
-// shader kind.  Per-unit aggregates are reduced per draw afterwards, so no
-// same-address atomics are on the hot path.
+// batches (one wavefront each) or naive chunks of 256 corners.  The draws are
+// grouped by variant (dedup mode and vertex program) through an order array;
+// a prepare kernel counts each draw's units and prefix-sums them in that
+// order, so every variant owns one contiguous range of units.  One persistent
+// kernel per variant, compiled for that variant alone (so its registers and
+// LDS are those of the variant, not of the widest one), deals its range out
+// to its workgroups in chunks of kFrameChunk units, round robin, finds each
+// unit's draw by binary search in an LDS copy of the range's draw bases, and
+// runs the single-draw device function.  Per-unit aggregates are reduced per
+// draw afterwards, so no same-address atomics are on the hot path.
 #pragma once
 
 #include "vr_kernels.h"
@@ -21,6 +24,12 @@ enum FrameMode : uint32_t { kFrameSort = 0, kFrameHash = 1, kFramePHash = 2, kFr
 constexpr uint32_t kFrameNT = 256;
 constexpr uint32_t kFrameChunk = 4;      // consecutive units a workgroup takes at a time
 constexpr uint32_t kFrameMaxDraws = 4096;
+
+// One persistent launch of a frame: the draws of one variant (order
+// positions [lo, hi)), its kernel's LDS and its grid.
+struct FrameVariant {
+    uint32_t mode, kind, lo, hi, grid, unit_lds, ballot_stride, lds_total;
+};
 
 struct DrawDesc {
     const uint32_t *idx;
@@ -68,27 +77,28 @@ __device__ __forceinline__ void frame_draw_units(const DrawDesc &D, uint32_t &un
     units = D.mode == kFrameBallot ? (nb + 3) / 4 : nb;   // four wavefronts, four ballot batches
 }
 
-// One workgroup: per-draw unit and slot bases (exclusive scans), totals last.
-__global__ __launch_bounds__(1024) void k_frame_prepare(const DrawDesc *draws, uint32_t n, uint32_t *unit_base,
-                                                        uint32_t *slot_base, uint32_t *err) {
+// One workgroup: unit and slot bases of the draws in variant order
+// (position k is draw order[k]), totals last.
+__global__ __launch_bounds__(1024) void k_frame_prepare(const DrawDesc *draws, const uint32_t *order, uint32_t n,
+                                                        uint32_t *unit_base, uint32_t *slot_base, uint32_t *err) {
     __shared__ uint32_t tmp[16];
     const uint32_t E = (n + 1023) / 1024;
     const uint32_t lo = min(n, threadIdx.x * E), hi = min(n, lo + E);
     uint32_t su = 0, ss = 0;
-    for (uint32_t d = lo; d < hi; ++d) {
+    for (uint32_t k = lo; k < hi; ++k) {
         uint32_t u, s;
-        frame_draw_units(draws[d], u, s, err);
+        frame_draw_units(draws[order[k]], u, s, err);
         su += u;
         ss += s;
     }
     uint32_t tu, ts;
     uint32_t ru = block_excl_scan<1024>(su, tmp, tu);
     uint32_t rs = block_excl_scan<1024>(ss, tmp, ts);
-    for (uint32_t d = lo; d < hi; ++d) {
+    for (uint32_t k = lo; k < hi; ++k) {
         uint32_t u, s;
-        frame_draw_units(draws[d], u, s, err);
-        unit_base[d] = ru;
-        slot_base[d] = rs;
+        frame_draw_units(draws[order[k]], u, s, err);
+        unit_base[k] = ru;
+        slot_base[k] = rs;
         ru += u;
         rs += s;
     }
@@ -121,69 +131,68 @@ __device__ __forceinline__ DrawArgs frame_args(const DrawDesc &D, unsigned long 
     return A;
 }
 
-template <int KIND>
-__device__ __forceinline__ void frame_unit_kind(const DrawDesc &D, const DrawArgs &A, const vr_shader_params &sh,
-                                                uint32_t local, uint32_t nb, unsigned char *smem,
-                                                uint32_t ballot_stride) {
-    switch (D.mode) {
-    case kFrameSort: dedup_unit<kFrameNT, kSort, KIND>(A, sh, local, nb, smem); break;
-    case kFrameHash: dedup_unit<kFrameNT, kHash, KIND>(A, sh, local, nb, smem); break;
-    case kFramePHash: dedup_unit<kFrameNT, kPHash, KIND>(A, sh, local, nb, smem); break;
-    case kFrameBallot: {
+template <int MODE, int KIND>
+__device__ __forceinline__ void frame_unit(const DrawArgs &A, const vr_shader_params &sh, uint32_t local,
+                                           uint32_t nb, unsigned char *smem, uint32_t ballot_stride) {
+    if (MODE == kFrameSort) {
+        dedup_unit<kFrameNT, kSort, KIND>(A, sh, local, nb, smem);
+    } else if (MODE == kFrameHash) {
+        dedup_unit<kFrameNT, kHash, KIND>(A, sh, local, nb, smem);
+    } else if (MODE == kFramePHash) {
+        dedup_unit<kFrameNT, kPHash, KIND>(A, sh, local, nb, smem);
+    } else if (MODE == kFrameBallot) {
         const uint32_t w = threadIdx.x / kWave;
         const uint32_t b = 4 * local + w;
         unsigned char *mine = smem + w * ballot_stride;
         if (b < nb) ballot_batch<KIND>(A, sh, b, nb, mine);
         __syncthreads();
-        break;
-    }
-    default: {
+    } else {
         const unsigned long long agg = naive_chunk<KIND>(A, sh, local, (f4 *)smem);
         if (threadIdx.x == 0) A.agg[local] = agg;
-        break;
-    }
     }
 }
 
-// The persistent frame kernel.  Dynamic LDS: the largest unit layout of the
-// frame, then the draw bases (n + 1 words).
-__global__ __launch_bounds__(kFrameNT) void k_frame(const DrawDesc *draws, uint32_t n,
-                                                    const vr_shader_params *shaders, const uint32_t *unit_base,
-                                                    const uint32_t *slot_base, unsigned long long *agg,
-                                                    uint32_t unit_lds, uint32_t ballot_stride, uint32_t *err,
+// The persistent kernel of one variant: the draws at order positions
+// [lo, hi), whose units are unit_base[lo] .. unit_base[hi] - 1.  Dynamic LDS:
+// the variant's largest unit layout, then its draw bases (hi - lo + 1 words).
+template <int MODE, int KIND>
+__global__ __launch_bounds__(kFrameNT) void k_frame(const DrawDesc *draws, const uint32_t *order, uint32_t lo,
+                                                    uint32_t hi, const vr_shader_params *shaders,
+                                                    const uint32_t *unit_base, const uint32_t *slot_base,
+                                                    unsigned long long *agg, uint32_t unit_lds,
+                                                    uint32_t ballot_stride, uint32_t *err,
                                                     unsigned long long *total_inv) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const uint32_t m = hi - lo;
     uint32_t *s_base = (uint32_t *)(smem + unit_lds);
-    for (uint32_t d = threadIdx.x; d <= n; d += kFrameNT) s_base[d] = unit_base[d];
+    for (uint32_t k = threadIdx.x; k <= m; k += kFrameNT) s_base[k] = unit_base[lo + k];
     __syncthreads();
-    const uint32_t U = s_base[n];
+    const uint32_t U = s_base[m];
     const uint32_t G = gridDim.x;
-    for (uint32_t c0 = blockIdx.x * kFrameChunk; c0 < U; c0 += G * kFrameChunk) {
-        // the draw of unit c0: largest d with s_base[d] <= c0
-        uint32_t lo = 0, hi = n;   // invariant: s_base[lo] <= c0 < s_base[hi]
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) / 2;
-            if (s_base[mid] <= c0) lo = mid;
-            else hi = mid;
+    for (uint32_t c0 = s_base[0] + blockIdx.x * kFrameChunk; c0 < U; c0 += G * kFrameChunk) {
+        // the draw of unit c0: largest k with s_base[k] <= c0
+        uint32_t a = 0, b = m;   // invariant: s_base[a] <= c0 < s_base[b]
+        while (b - a > 1) {
+            const uint32_t mid = (a + b) / 2;
+            if (s_base[mid] <= c0) a = mid;
+            else b = mid;
         }
-        uint32_t d = lo;
+        uint32_t k = a;
         for (uint32_t u = c0; u < min(U, c0 + kFrameChunk); ++u) {
-            while (u >= s_base[d + 1]) ++d;   // units of empty draws are skipped
-            const DrawDesc D = draws[d];
-            const DrawArgs A = frame_args(D, agg + slot_base[d], err, total_inv);
-            const vr_shader_params &sh = shaders[D.shader];
-            const uint32_t nb = slot_base[d + 1] - slot_base[d];
-            const uint32_t local = u - s_base[d];
-            if (D.kind == 0) frame_unit_kind<0>(D, A, sh, local, nb, smem, ballot_stride);
-            else if (D.kind == 1) frame_unit_kind<1>(D, A, sh, local, nb, smem, ballot_stride);
-            else frame_unit_kind<2>(D, A, sh, local, nb, smem, ballot_stride);
+            while (u >= s_base[k + 1]) ++k;   // units of empty draws are skipped
+            const DrawDesc D = draws[order[lo + k]];
+            const DrawArgs A = frame_args(D, agg + slot_base[lo + k], err, total_inv);
+            const uint32_t nb = slot_base[lo + k + 1] - slot_base[lo + k];
+            frame_unit<MODE, KIND>(A, shaders[D.shader], u - s_base[k], nb, smem, ballot_stride);
         }
     }
 }
 
-// Per draw: counters = the sum of its aggregates; dtot[d] = its invocations.
-__global__ __launch_bounds__(64) void k_frame_finish(const DrawDesc *draws, const uint32_t *slot_base,
-                                                     const unsigned long long *agg, unsigned long long *dtot) {
+// Per draw (order position k): counters = the sum of its aggregates;
+// dtot[k] = its invocations.
+__global__ __launch_bounds__(64) void k_frame_finish(const DrawDesc *draws, const uint32_t *order,
+                                                     const uint32_t *slot_base, const unsigned long long *agg,
+                                                     unsigned long long *dtot) {
     const uint32_t d = blockIdx.x;
     unsigned long long sum = 0;
     for (uint32_t i = slot_base[d] + lane_id(); i < slot_base[d + 1]; i += kWave) sum += agg[i];
@@ -191,7 +200,7 @@ __global__ __launch_bounds__(64) void k_frame_finish(const DrawDesc *draws, cons
     for (int s = 32; s > 0; s >>= 1) sum += __shfl_xor(sum, s, kWave);
     if (lane_id() == 0) {
         const unsigned long long inv = sum & 0xFFFFFFFFull, units = sum >> 32;
-        unsigned long long *c = draws[d].counters;
+        unsigned long long *c = draws[order[d]].counters;
         if (c) {
             c[0] = inv;
             c[1] = units;

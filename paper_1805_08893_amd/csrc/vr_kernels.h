@@ -124,7 +124,7 @@ __device__ __forceinline__ void shade_to_lds(const DrawArgs &A, const vr_shader_
 template <int NT, typename LocalT>
 __device__ __forceinline__ void write_unit(const DrawArgs &A, uint32_t t0, uint32_t ntri, const LocalT *s_local,
                                            const f4 *s_sv, uint32_t inv, uint32_t vbase, uint32_t unit,
-                                           uint32_t tid) {
+                                           uint32_t tid, bool verts_written = false) {
     const uint32_t ncorner = 3 * ntri;
     if (A.corners) {
         // float4 q of the span is part q % 3 of corner q / 3.  Lane tid takes
@@ -163,7 +163,7 @@ __device__ __forceinline__ void write_unit(const DrawArgs &A, uint32_t t0, uint3
             if (A.local_idx) A.local_idx[3ull * t0 + k] = (uint16_t)l;
         }
     }
-    if (A.verts) {
+    if (A.verts && !verts_written) {
         f4 *dst = A.verts + 3ull * vbase;
         for (uint32_t q = tid; q < 3 * inv; q += NT) __builtin_nontemporal_store(s_sv[q], dst + q);
     }
@@ -343,12 +343,14 @@ __host__ __device__ inline uint32_t sort_groups(uint32_t max_idx, uint32_t nt) {
 // shaded vertices (written after deduplication) share their region with
 // what deduplication alone uses: the indices, then the sort's two position
 // buffers and its per-digit counts (uint8) and offsets (uint16), or the
-// hash table and the first-position words.
+// hash table and the first-position words.  sv_rows shaded vertices are
+// kept: every unique vertex of a unit when corners are assembled, else one
+// stage of nt rows through which the shaded vertices stream out.
 __host__ __device__ inline DedupLds dedup_lds_layout(int mode, uint32_t max_idx, uint32_t max_uniq,
-                                                     uint32_t hash_bits, uint32_t nt) {
+                                                     uint32_t hash_bits, uint32_t nt, uint32_t sv_rows) {
     DedupLds L{};
     uint32_t off = 0;
-    L.local = off; off += align16(2 * max_idx);   // uint16: hash slots < 4096, then ids < max_idx
+    L.local = off; off += align16(2 * max_idx);   // uint16: hash slots < 8192, then ids < max_idx
     L.uniq = off;  off += align16(4 * max_uniq);
     L.sv = off;
     uint32_t d = off;
@@ -362,7 +364,7 @@ __host__ __device__ inline DedupLds dedup_lds_layout(int mode, uint32_t max_idx,
         L.table = d; d += align16(4u << hash_bits);
         L.first = d; d += align16(4u << hash_bits);
     }
-    off = max(align16(off + 48 * max_uniq), align16(d));
+    off = max(align16(off + 48 * sv_rows), align16(d));
     L.tmp = off;  off += 64;
     L.total = off;
     return L;
@@ -493,7 +495,9 @@ __device__ __forceinline__ const uint16_t *radix_passes(const uint32_t *s_keys, 
 template <int NT, int MODE, int KIND>
 __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_params &sh, uint32_t u, uint32_t nb,
                                            unsigned char *smem) {
-    const DedupLds L = dedup_lds_layout(MODE, A.max_idx, A.max_uniq, A.hash_bits, NT);
+    // without corners the shaded vertices stream out through an NT-row stage
+    const bool stream = A.corners == nullptr;
+    const DedupLds L = dedup_lds_layout(MODE, A.max_idx, A.max_uniq, A.hash_bits, NT, stream ? NT : A.max_uniq);
     uint32_t *s_keys = (uint32_t *)(smem + L.keys);
     uint16_t *s_local = (uint16_t *)(smem + L.local);
     uint32_t *s_uniq = (uint32_t *)(smem + L.uniq);
@@ -679,17 +683,36 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
             inv = 0;
         }
         // publish this unit's invocation count early; resolve after shading
+        // (before it when the shaded vertices stream out)
         if (A.need_prefix && tid == 0) lookback_publish(A.status, u, (1ull << 32) | inv);
         __syncthreads();
-        for (uint32_t j = tid; j < inv; j += NT) shade_to_lds<KIND>(A, sh, s_uniq[j], s_sv + 3 * j);
-        if (tid == 0) {
+        if (!stream)
+            for (uint32_t j = tid; j < inv; j += NT) shade_to_lds<KIND>(A, sh, s_uniq[j], s_sv + 3 * j);
+        if (tid < kWave) {   // the first wavefront, whole (NT >= 64)
             uint32_t vb = 0;
             if (A.need_prefix) vb = (uint32_t)lookback_resolve(A.status, u, (1ull << 32) | inv, A.err);
-            s_vbase = vb;
-            if (A.unit_offsets && u + 1 == nb) A.unit_offsets[nb] = A.T;
+            if (tid == 0) {
+                s_vbase = vb;
+                if (A.unit_offsets && u + 1 == nb) A.unit_offsets[nb] = A.T;
+            }
         }
         __syncthreads();
-        if (fits && (inv > 0 || n == 0)) write_unit<NT>(A, t0, t1 - t0, s_local, s_sv, inv, s_vbase, u, tid);
+        if (stream) {
+            // NT unique vertices at a time: shaded into the stage, then stored
+            // as one contiguous span of rows
+            f4 *dst = A.verts ? A.verts + 3ull * s_vbase : nullptr;
+            for (uint32_t j0 = 0; j0 < inv; j0 += NT) {
+                const uint32_t rows = min((uint32_t)NT, inv - j0);
+                if (tid < rows) shade_to_lds<KIND>(A, sh, s_uniq[j0 + tid], s_sv + 3 * tid);
+                __syncthreads();
+                if (dst)
+                    for (uint32_t q = tid; q < 3 * rows; q += NT)
+                        __builtin_nontemporal_store(s_sv[q], dst + 3ull * j0 + q);
+                __syncthreads();
+            }
+        }
+        if (fits && (inv > 0 || n == 0))
+            write_unit<NT>(A, t0, t1 - t0, s_local, s_sv, inv, s_vbase, u, tid, stream);
         if (tid == 0 && A.agg) A.agg[u] = (1ull << 32) | inv;
         __syncthreads();   // the caller may reuse the LDS for the next unit
     }
@@ -861,12 +884,9 @@ __device__ __forceinline__ void ballot_batch(const DrawArgs &A, const vr_shader_
             cur = ballot_round(A, t0, cur, t1, s_keys, pre, s_new, nullptr, st);
             inv += st.fill;
         }
-        uint64_t ex = 0;
-        if (lane == 0) {
-            const uint64_t agg = ((uint64_t)rounds << 32) | inv;
-            lookback_publish(A.status, b, agg);
-            ex = lookback_resolve(A.status, b, agg, A.err);
-        }
+        const uint64_t agg = ((uint64_t)rounds << 32) | inv;
+        if (lane == 0) lookback_publish(A.status, b, agg);
+        const uint64_t ex = lookback_resolve(A.status, b, agg, A.err);
         vbase = __builtin_amdgcn_readfirstlane((uint32_t)ex);
         ubase = __builtin_amdgcn_readfirstlane((uint32_t)((ex >> 32) & 0x3FFFFFFFu));
     }

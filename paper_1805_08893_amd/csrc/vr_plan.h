@@ -8,17 +8,21 @@
 // exactly, in parallel, in three steps:
 //
 //  1. next(c) for every c (k_plan_next).  A workgroup stages the indices of
-//     256 starts plus N_pmax triangles in LDS, finds every corner's previous
-//     occurrence in that window (hash slots, bucketed by a counting sort),
-//     and one lane per start adds up the corners whose previous occurrence
-//     lies before the start until the budget would be exceeded.
+//     a block of starts plus N_pmax triangles in LDS and finds every corner's
+//     previous and next occurrence in that window (hash slots, bucketed by a
+//     counting sort).  The distinct count of the full N_pmax window of every
+//     start follows from a difference array; where it is within N_u, next(c)
+//     is the window's end.  Each lane then sweeps a few consecutive starts
+//     with two pointers: moving the start past a triangle drops its corners
+//     that were new and makes new the next occurrences of its corners inside
+//     the batch; the end then advances while the budget holds.
 //  2. Transfer tables (k_plan_table, k_plan_compose).  The triangles are cut
 //     into segments of L >= N_pmax triangles.  The chain's state at a
 //     segment boundary is its first position at or after the boundary, which
 //     lies within N_pmax triangles of it.  For every possible entry offset a
-//     table gives the exit offset at the segment's end (pointer jumping over
-//     next() in LDS); tables of 32 consecutive ranges are composed into one,
-//     level by level, until at most 32 remain.
+//     table gives the exit offset at the segment's end (one lane per entry
+//     follows next() in LDS); tables of consecutive ranges are composed into
+//     one, level by level, until few remain.
 //  3. Resolution (k_plan_top, k_plan_resolve, k_plan_emit, k_plan_pack).  The
 //     top tables are applied in order from entry 0, entries are pushed down
 //     the levels, every segment walks next() from its entry to list its batch
@@ -31,22 +35,55 @@
 
 namespace vr {
 
-constexpr uint32_t kNextBlock = 256;                         // starts per workgroup
-constexpr uint32_t kFanIn = 32;                              // tables composed per group
 constexpr uint16_t kEnd = 0xFFFF;                            // table value: the chain has ended
-constexpr uint32_t kNone = 0xFFFF;                           // no previous occurrence
+constexpr uint32_t kNone = 0xFFFF;                           // no previous / next occurrence
 
-// Window of k_plan_next for primitive caps up to TM triangles: the staged
-// triangles, and a power-of-two hash table that holds every staged corner.
-template <uint32_t TM>
-struct NextWindow {
-    static constexpr uint32_t tris = kNextBlock + TM;
-    static constexpr uint32_t bits = 3 * tris <= 2048 ? 11 : 12;
+constexpr uint32_t ceil_log2(uint32_t x) { return x <= 1 ? 0 : 1 + ceil_log2((x + 1) / 2); }
+
+// Primitive-cap classes: the planner's kernels are instantiated for caps up
+// to 256, 512, 1024, 2048 and 4096 triangles.
+__host__ __device__ inline uint32_t plan_class(uint32_t tmax) {
+    uint32_t c = 256;
+    while (c < tmax) c <<= 1;
+    return c;
+}
+
+// Tables composed per group: as many as fit in 64 KB of LDS, at most 32.
+__host__ __device__ inline uint32_t plan_fan_in(uint32_t tmax) {
+    const uint32_t f = 32768u / tmax;
+    return f < 2 ? 2 : (f > 32 ? 32 : f);
+}
+
+// k_plan_next for caps up to TMC triangles: one start per thread, the
+// window of the block's starts plus TMC triangles, corners per thread, a
+// power-of-two hash table at most 8/9 full.
+template <uint32_t TMC>
+struct NextClass {
+    static constexpr uint32_t threads = TMC <= 1024 ? 256 : 512;
+    static constexpr uint32_t starts = threads;
+    static constexpr uint32_t tris = starts + TMC;
+    static constexpr uint32_t corners = 3 * tris;
+    static constexpr uint32_t per = corners / threads;
+    static constexpr uint32_t bits = ceil_log2(corners + corners / 8);
     static constexpr uint32_t slots = 1u << bits;
-    static constexpr uint32_t per = 3 * tris / 256;            // corners per thread
+    // LDS: keys -> corner positions grouped by slot (+ the difference array),
+    // the hash table -> bucket starts | ends, slot counts -> previous
+    // occurrences packed per triangle (three 16-bit positions in 64 bits)
     static constexpr uint32_t prev_words = (slots / 4 > tris + 4) ? slots / 4 : tris + 4;
-    static_assert(slots >= 3 * tris, "hash table must hold every staged corner");
-    static_assert((3 * tris) % 256 == 0, "corners split evenly over the threads");
+    static constexpr uint32_t lds = 4 * corners + 4 * slots + 8 * prev_words + 64;
+    static_assert(corners % threads == 0, "corners split evenly over the threads");
+    static_assert(slots >= corners + corners / 8 && corners < kNone, "window fits the table and 16-bit positions");
+    static_assert(2 * corners + 4 * (starts + 1) <= 4 * corners, "difference array fits behind the positions");
+    static_assert(lds <= 160 * 1024, "window fits the LDS");
+};
+
+// k_plan_check for caps up to TMC triangles: one window per workgroup.
+template <uint32_t TMC>
+struct CheckClass {
+    static constexpr uint32_t threads = TMC <= 1024 ? 256 : 1024;
+    static constexpr uint32_t per = 3 * TMC / threads;
+    static constexpr uint32_t bits = ceil_log2(3 * TMC) + 1 < 14 ? ceil_log2(3 * TMC) + 1 : 14;
+    static_assert((1u << bits) >= 3 * TMC + 3 * TMC / 4, "check table must hold every corner");
 };
 
 struct PlanArgs {
@@ -77,13 +114,12 @@ __device__ __forceinline__ uint32_t seg_hi(const PlanArgs &P, uint32_t s) { retu
 // (every writer stores the same value).  Indices >= V raise
 // VR_ERR_INDEX_RANGE here, since the general pass may not run.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kCheckBits = 11;                             // 2048 slots >= 3 * N_pmax
-constexpr uint32_t kCheckPer = 3 * VR_MAX_BATCH_DYNAMIC / 256;  // corners per thread
-static_assert((1u << kCheckBits) >= 3 * VR_MAX_BATCH_DYNAMIC, "check table must hold every corner");
-
-__global__ __launch_bounds__(256) void k_plan_check(PlanArgs P, uint32_t *plan) {
-    __shared__ uint32_t s_tab[1u << kCheckBits];
-    __shared__ uint32_t s_tmp[4];
+template <uint32_t TMC>
+__global__ __launch_bounds__(CheckClass<TMC>::threads) void k_plan_check(PlanArgs P, uint32_t *plan) {
+    using C = CheckClass<TMC>;
+    constexpr uint32_t NT = C::threads, kPer = C::per, kBits = C::bits;
+    __shared__ uint32_t s_tab[1u << kBits];
+    __shared__ uint32_t s_tmp[NT / kWave];
     const uint32_t tid = threadIdx.x;
     const uint32_t t0 = blockIdx.x * P.tmax, t1 = min(P.T, t0 + P.tmax);
     const uint32_t n = 3 * (t1 - t0);
@@ -98,62 +134,63 @@ __global__ __launch_bounds__(256) void k_plan_check(PlanArgs P, uint32_t *plan) 
         }
     }
     // every load is issued before the first is checked, so their latencies overlap
-    uint32_t key[kCheckPer];
+    uint32_t key[kPer];
 #pragma unroll
-    for (uint32_t k = 0; k < kCheckPer; ++k) {
-        const uint32_t i = tid + 256 * k;
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t i = tid + NT * k;
         key[k] = i < n ? P.idx[3ull * t0 + i] : 0u;
     }
 #pragma unroll
-    for (uint32_t k = 0; k < kCheckPer; ++k) {
-        if (tid + 256 * k < n && key[k] >= P.V) {
+    for (uint32_t k = 0; k < kPer; ++k) {
+        if (tid + NT * k < n && key[k] >= P.V) {
             raise_error(P.err, VR_ERR_INDEX_RANGE);
             key[k] = 0;
         }
     }
-    for (uint32_t q = tid; q < (1u << kCheckBits); q += 256) s_tab[q] = kEmpty;
+    for (uint32_t q = tid; q < (1u << kBits); q += NT) s_tab[q] = kEmpty;
     __syncthreads();
-    uint32_t slot[kCheckPer], pending = 0, fresh = 0;
+    uint32_t slot[kPer], pending = 0, fresh = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < kCheckPer; ++k) {
-        slot[k] = hash_slot(key[k], kCheckBits);
-        if (tid + 256 * k < n) pending |= 1u << k;
+    for (uint32_t k = 0; k < kPer; ++k) {
+        slot[k] = hash_slot(key[k], kBits);
+        if (tid + NT * k < n) pending |= 1u << k;
     }
     while (pending) {   // lockstep linear probing; the table never fills
 #pragma unroll
-        for (uint32_t k = 0; k < kCheckPer; ++k) {
+        for (uint32_t k = 0; k < kPer; ++k) {
             if (pending & (1u << k)) {
                 const uint32_t prev = atomicCAS(&s_tab[slot[k]], kEmpty, key[k]);
                 if (prev == kEmpty || prev == key[k]) {
                     fresh += prev == kEmpty;
                     pending &= ~(1u << k);
                 } else {
-                    slot[k] = (slot[k] + 1) & ((1u << kCheckBits) - 1);
+                    slot[k] = (slot[k] + 1) & ((1u << kBits) - 1);
                 }
             }
         }
     }
     uint32_t distinct;
-    block_excl_scan<256>(fresh, s_tmp, distinct);
+    block_excl_scan<NT>(fresh, s_tmp, distinct);
     if (tid == 0 && distinct > P.cap) *P.fail = P.epoch;
 }
 
 // ---------------------------------------------------------------------------
 // 1. next(c) for every start c
 // ---------------------------------------------------------------------------
-template <uint32_t TM>
-__global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
-    using Win = NextWindow<TM>;
-    constexpr uint32_t kNextTris = Win::tris, kNextSlots = Win::slots;
+template <uint32_t TMC>
+__global__ __launch_bounds__(NextClass<TMC>::threads) void k_plan_next(PlanArgs P) {
+    using Win = NextClass<TMC>;
+    constexpr uint32_t NT = Win::threads, kNextBlock = Win::starts, kNextTris = Win::tris, kNextSlots = Win::slots;
     if (plan_is_aligned(P.fail, P.epoch)) return;
     // LDS regions are reused once their first contents are dead:
     //   s_a: indices (insert) -> corner positions grouped by slot + start counts
     //   s_tab: keys (insert) -> bucket starts | bucket ends (2 x uint16)
     //   s_cnt: slot counts -> 3 x 16-bit previous occurrence per triangle
-    __shared__ uint32_t s_a[3 * kNextTris];
-    __shared__ uint32_t s_tab[kNextSlots];
-    __shared__ unsigned long long s_cntprev[Win::prev_words];
-    __shared__ uint32_t s_tmp[4];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    uint32_t *s_a = (uint32_t *)smem;
+    uint32_t *s_tab = s_a + 3 * kNextTris;
+    unsigned long long *s_cntprev = (unsigned long long *)(s_tab + kNextSlots);
+    uint32_t *s_tmp = (uint32_t *)(s_cntprev + Win::prev_words);
     uint16_t *s_cnt = (uint16_t *)s_cntprev;
     unsigned long long *s_prev = s_cntprev;
     uint32_t *s_key = s_a;
@@ -166,16 +203,16 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
     const uint32_t n = 3 * (r1 - c0);
 
     // three loads per thread issued before the first is checked (latencies overlap)
-    for (uint32_t i0 = 0; i0 < n; i0 += 3 * 256) {
+    for (uint32_t i0 = 0; i0 < n; i0 += 3 * NT) {
         uint32_t v[3];
 #pragma unroll
         for (uint32_t r = 0; r < 3; ++r) {
-            const uint32_t i = i0 + r * 256 + tid;
+            const uint32_t i = i0 + r * NT + tid;
             v[r] = i < n ? P.idx[3ull * c0 + i] : 0u;
         }
 #pragma unroll
         for (uint32_t r = 0; r < 3; ++r) {
-            const uint32_t i = i0 + r * 256 + tid;
+            const uint32_t i = i0 + r * NT + tid;
             if (i < n) {
                 if (v[r] >= P.V) {
                     raise_error(P.err, VR_ERR_INDEX_RANGE);
@@ -185,37 +222,37 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
             }
         }
     }
-    for (uint32_t s = tid; s < kNextSlots; s += 256) {
+    for (uint32_t s = tid; s < kNextSlots; s += NT) {
         s_tab[s] = kEmpty;
         s_cnt[s] = 0;
     }
     __syncthreads();
-    // insertion: every thread owns corners tid + 256*k (k < kPer) and probes
+    // insertion: every thread owns corners tid + NT*k (k < kPer) and probes
     // them in lockstep rounds so their LDS round trips overlap
     constexpr uint32_t kBits = Win::bits;
     constexpr uint32_t kPer = Win::per;
     uint32_t key[kPer], slot[kPer];
-    uint32_t pending = 0;
+    uint64_t pending = 0;
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
-        const uint32_t i = tid + 256 * k;
+        const uint32_t i = tid + NT * k;
         key[k] = i < n ? s_key[i] : 0u;
         slot[k] = hash_slot(key[k], kBits);
-        if (i < n) pending |= 1u << k;
+        if (i < n) pending |= 1ull << k;
     }
     while (pending) {
 #pragma unroll
         for (uint32_t k = 0; k < kPer; ++k) {
-            if (pending & (1u << k)) {
+            if (pending & (1ull << k)) {
                 const uint32_t prev = atomicCAS(&s_tab[slot[k]], kEmpty, key[k]);
-                if (prev == kEmpty || prev == key[k]) pending &= ~(1u << k);
+                if (prev == kEmpty || prev == key[k]) pending &= ~(1ull << k);
                 else slot[k] = (slot[k] + 1) & (kNextSlots - 1);
             }
         }
     }
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
-        const uint32_t i = tid + 256 * k;
+        const uint32_t i = tid + NT * k;
         if (i < n) {
             // counts per slot (16-bit LDS words are updated through their 32-bit word)
             atomicAdd((uint32_t *)&s_cnt[slot[k] & ~1u], (slot[k] & 1u) ? 0x10000u : 1u);
@@ -223,11 +260,11 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
     }
     __syncthreads();
     {   // bucket starts: exclusive scan of the counts, 16 slots per thread
-        constexpr uint32_t E = kNextSlots / 256;
+        constexpr uint32_t E = kNextSlots / NT;
         uint32_t sum = 0;
         for (uint32_t j = 0; j < E; ++j) sum += s_cnt[tid * E + j];
         uint32_t total;
-        uint32_t run = block_excl_scan<256>(sum, s_tmp, total);
+        uint32_t run = block_excl_scan<NT>(sum, s_tmp, total);
         for (uint32_t j = 0; j < E; ++j) {
             const uint32_t cnt = s_cnt[tid * E + j];
             s_start[tid * E + j] = (uint16_t)run;
@@ -238,14 +275,14 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
     __syncthreads();
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
-        const uint32_t i = tid + 256 * k;
+        const uint32_t i = tid + NT * k;
         if (i < n) {
             const uint32_t sl = slot[k];
             const uint32_t old = atomicAdd((uint32_t *)&s_end[sl & ~1u], (sl & 1u) ? 0x10000u : 1u);
             s_arr[(sl & 1u) ? (old >> 16) : (old & 0xFFFFu)] = (uint16_t)i;
         }
     }
-    for (uint32_t c = tid; c <= kNextBlock; c += 256) s_diff[c] = 0;
+    for (uint32_t c = tid; c <= kNextBlock; c += NT) s_diff[c] = 0;
     __syncthreads();
     // previous occurrence of every corner inside the window (bucket order is
     // arbitrary, so take the largest position below the corner's own), and
@@ -257,7 +294,7 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
     uint32_t q[kPer], qe[kPer], best[kPer];
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
-        const uint32_t i = tid + 256 * k;
+        const uint32_t i = tid + NT * k;
         q[k] = i < n ? s_start[slot[k]] : 0u;
         qe[k] = i < n ? s_end[slot[k]] : 0u;
         best[k] = kNone;
@@ -267,7 +304,7 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
 #pragma unroll
         for (uint32_t k = 0; k < kPer; ++k) {
             if (q[k] < qe[k]) {
-                const uint32_t i = tid + 256 * k;
+                const uint32_t i = tid + NT * k;
                 const uint32_t a = s_arr[q[k]++];
                 if (a < i && (best[k] == kNone || a > best[k])) best[k] = a;
                 more |= q[k] < qe[k];
@@ -276,7 +313,7 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
     }
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
-        const uint32_t i = tid + 256 * k;
+        const uint32_t i = tid + NT * k;
         if (i < n) {
             ((uint16_t *)s_prev)[4 * (i / 3) + i % 3] = (uint16_t)best[k];
             const uint32_t lo_prev = best[k] == kNone ? 0u : best[k] / 3 + 1;
@@ -295,35 +332,57 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
     {
         uint32_t total;
         const int d = s_diff[tid];
-        dfull = block_excl_scan<256>((uint32_t)d, s_tmp, total) + (uint32_t)d;
+        dfull = block_excl_scan<NT>((uint32_t)d, s_tmp, total) + (uint32_t)d;
     }
     const uint32_t c = c0 + tid;
     if (c < P.T) {
         const uint32_t lim = min(P.T, c + P.tmax);
         uint32_t t = lim;
         if (dfull > P.cap) {
-            // the budget breaks inside the window: scan for the triangle that
-            // breaks it (kNone + 1 wraps to 0, so a missing previous occurrence
-            // always counts as new)
+            // the budget breaks inside the window (kNone + 1 wraps to 0, so a
+            // missing previous occurrence always counts as new).  Each corner
+            // counts on its own (new iff its previous occurrence lies before the
+            // start), so the count of a shorter batch is the window's count
+            // minus the new corners of the triangles dropped from its end.
+            // Where the window is at most twice over the budget the cut is
+            // found from the end, else from the start.
             const uint32_t first = 3 * tid;
-            uint32_t distinct = 0;
-            t = c;
-            bool stop = false;
-            while (!stop && t < lim) {
-                unsigned long long pr[4];
+            auto fresh = [&](unsigned long long x) {
+                return ((uint32_t)((x + 1) & 0xFFFF) <= first) + ((uint32_t)(((x >> 16) + 1) & 0xFFFF) <= first) +
+                       ((uint32_t)(((x >> 32) + 1) & 0xFFFF) <= first);
+            };
+            if (dfull - P.cap <= P.cap) {
+                uint32_t distinct = dfull;
+                t = lim;
+                while (distinct > P.cap) {   // ends by t = c + 1: one triangle never exceeds N_u >= 3
+                    unsigned long long pr[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) pr[u] = s_prev[t - c0 + u];
+                    for (int u = 0; u < 4; ++u) pr[u] = t > c + u ? s_prev[t - 1 - u - c0] : 0ull;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (!stop && t < lim) {
-                        const unsigned long long x = pr[u];
-                        const uint32_t f = ((uint32_t)((x + 1) & 0xFFFF) <= first) +
-                                           ((uint32_t)(((x >> 16) + 1) & 0xFFFF) <= first) +
-                                           ((uint32_t)(((x >> 32) + 1) & 0xFFFF) <= first);
-                        if (distinct + f > P.cap) stop = true;
-                        else {
-                            distinct += f;
-                            ++t;
+                    for (int u = 0; u < 4; ++u) {
+                        if (distinct > P.cap) {
+                            distinct -= fresh(pr[u]);
+                            --t;
+                        }
+                    }
+                }
+            } else {
+                uint32_t distinct = 0;
+                t = c;
+                bool stop = false;
+                while (!stop && t < lim) {
+                    unsigned long long pr[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) pr[u] = s_prev[t - c0 + u];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (!stop && t < lim) {
+                            const uint32_t f = fresh(pr[u]);
+                            if (distinct + f > P.cap) stop = true;
+                            else {
+                                distinct += f;
+                                ++t;
+                            }
                         }
                     }
                 }
@@ -337,48 +396,36 @@ __global__ __launch_bounds__(256) void k_plan_next(PlanArgs P) {
 // 2. Transfer tables.  Table layout: tmax entries of uint16 per range; entry
 // j = the chain's first position at or after the range's start boundary is
 // boundary + j; value = its first position at or after the range's end
-// boundary minus that boundary, or kEnd once the chain has reached T.
+// boundary minus that boundary, or kEnd once the chain has reached T.  One
+// lane per entry follows next() through the segment (staged in LDS).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_plan_table(PlanArgs P, uint16_t *tab) {
-    extern __shared__ uint32_t s_ptr[];   // seg_len entries
+    extern __shared__ uint32_t s_nx[];   // seg_len entries
     if (plan_is_aligned(P.fail, P.epoch)) return;
-    constexpr uint32_t kDone = 0x80000000u;
     const uint32_t s = blockIdx.x;
     const uint32_t b = seg_lo(P, s), e = seg_hi(P, s), len = e - b;
-    for (uint32_t i = threadIdx.x; i < len; i += 256) {
-        const uint32_t nx = P.next[b + i];
-        s_ptr[i] = nx >= e ? (kDone | (nx - e)) : (nx - b);
-    }
+    for (uint32_t i = threadIdx.x; i < len; i += 256) s_nx[i] = P.next[b + i];
     __syncthreads();
-    // pointer jumping: every position ends up holding its exit offset
-    uint32_t rounds = 1;
-    while ((1u << rounds) < len) ++rounds;
-    for (uint32_t r = 0; r <= rounds; ++r) {
-        for (uint32_t i = threadIdx.x; i < len; i += 256) {
-            const uint32_t v = s_ptr[i];
-            if (!(v & kDone)) s_ptr[i] = s_ptr[v];
-        }
-        __syncthreads();
-    }
     for (uint32_t j = threadIdx.x; j < P.tmax; j += 256) {
         uint16_t out = kEnd;
         if (j < len) {
-            const uint32_t v = s_ptr[j];
-            const uint32_t exitpos = e + (v & ~kDone);
-            out = exitpos >= P.T ? kEnd : (uint16_t)(exitpos - e);
+            uint32_t x = b + j;
+            while (x < e) x = s_nx[x - b];
+            out = x >= P.T ? kEnd : (uint16_t)(x - e);
         }
         tab[(size_t)s * P.tmax + j] = out;
     }
 }
 
-// Composes tables [g*kFanIn, min(count, g*kFanIn + kFanIn)) of `in` into
-// table g of `out`.
+// Composes tables [g*fan, min(count, g*fan + fan)) of `in` into table g of
+// `out` (fan = plan_fan_in(tmax)).
 __global__ __launch_bounds__(512) void k_plan_compose(uint32_t tmax, uint32_t count, const uint16_t *in,
                                                       uint16_t *out, const uint32_t *fail, uint32_t epoch) {
-    extern __shared__ uint16_t s_t[];   // kFanIn * tmax
+    extern __shared__ uint16_t s_t[];   // fan * tmax
     if (plan_is_aligned(fail, epoch)) return;
+    const uint32_t fan = plan_fan_in(tmax);
     const uint32_t g = blockIdx.x;
-    const uint32_t k0 = g * kFanIn, k1 = min(count, k0 + kFanIn);
+    const uint32_t k0 = g * fan, k1 = min(count, k0 + fan);
     const uint32_t m = (k1 - k0) * tmax;
     for (uint32_t i = threadIdx.x; i < m; i += 512) s_t[i] = in[(size_t)k0 * tmax + i];
     __syncthreads();
@@ -389,7 +436,7 @@ __global__ __launch_bounds__(512) void k_plan_compose(uint32_t tmax, uint32_t co
     }
 }
 
-// One workgroup: applies the (at most kFanIn) top tables in order starting
+// One workgroup: applies the (at most fan) top tables in order starting
 // from entry 0 and records each table's entry.
 __global__ __launch_bounds__(256) void k_plan_top(uint32_t tmax, uint32_t count, const uint16_t *tab,
                                                   uint16_t *entry, const uint32_t *fail, uint32_t epoch) {
@@ -407,15 +454,16 @@ __global__ __launch_bounds__(256) void k_plan_top(uint32_t tmax, uint32_t count,
     }
 }
 
-// Pushes entries one level down: group g of `tab` (kFanIn tables) receives
-// its entry from up_entry[g] and records its members' entries.
+// Pushes entries one level down: group g of `tab` (fan tables) receives its
+// entry from up_entry[g] and records its members' entries.
 __global__ __launch_bounds__(256) void k_plan_resolve(uint32_t tmax, uint32_t count, const uint16_t *tab,
                                                       const uint16_t *up_entry, uint16_t *entry,
                                                       const uint32_t *fail, uint32_t epoch) {
     extern __shared__ uint16_t s_t[];
     if (plan_is_aligned(fail, epoch)) return;
+    const uint32_t fan = plan_fan_in(tmax);
     const uint32_t g = blockIdx.x;
-    const uint32_t k0 = g * kFanIn, k1 = min(count, k0 + kFanIn);
+    const uint32_t k0 = g * fan, k1 = min(count, k0 + fan);
     const uint32_t m = (k1 - k0) * tmax;
     for (uint32_t i = threadIdx.x; i < m; i += 256) s_t[i] = tab[(size_t)k0 * tmax + i];
     __syncthreads();

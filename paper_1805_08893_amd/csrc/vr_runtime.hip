@@ -203,7 +203,8 @@ vr_status check_args(vr_ctx *c, uint64_t num_indices, uint32_t num_vertices, con
     Resolved r;
     if (is_dynamic(strategy)) {
         r.nu = o.max_unique ? o.max_unique : default_max_unique(batch_tris);
-        if (r.nu < 3 || r.nu > VR_MAX_UNIQUE) return fail(c, VR_ERR_ARG, "max_unique %u outside 3..512", r.nu);
+        if (r.nu < 3 || r.nu > VR_MAX_UNIQUE)
+            return fail(c, VR_ERR_ARG, "max_unique %u outside 3..%u", r.nu, (unsigned)VR_MAX_UNIQUE);
         r.max_idx = 3 * batch_tris;
         r.max_uniq = std::min(r.nu, r.max_idx);
     } else {
@@ -213,8 +214,9 @@ vr_status check_args(vr_ctx *c, uint64_t num_indices, uint32_t num_vertices, con
     if (strategy == VR_NAIVE || strategy == VR_MULTI) r.max_idx = r.max_uniq = 3;
     if (o.hash_slots != 0) {
         const uint32_t need = is_dynamic(strategy) ? r.nu : 3u * batch_tris;
-        if ((o.hash_slots & (o.hash_slots - 1)) != 0 || o.hash_slots < need || o.hash_slots > 4096)
-            return fail(c, VR_ERR_ARG, "hash_slots %u: need a power of two in %u..4096", o.hash_slots, need);
+        if ((o.hash_slots & (o.hash_slots - 1)) != 0 || o.hash_slots < need || o.hash_slots > VR_MAX_HASH_SLOTS)
+            return fail(c, VR_ERR_ARG, "hash_slots %u: need a power of two in %u..%u", o.hash_slots, need,
+                        (unsigned)VR_MAX_HASH_SLOTS);
     }
     const uint64_t T = num_indices / 3;
     const uint64_t vneed = strategy == VR_MULTI ? (uint64_t)num_vertices : 3 * T;
@@ -228,10 +230,14 @@ vr_status check_args(vr_ctx *c, uint64_t num_indices, uint32_t num_vertices, con
     if (strategy != VR_NAIVE && strategy != VR_MULTI && !is_ballot(strategy)) {
         uint32_t want = o.wg_size ? o.wg_size : std::max<uint32_t>(64, std::min<uint32_t>(256, r.max_uniq));
         uint32_t nt = 64;
-        while (nt * 2 <= want && nt < 512) nt *= 2;
-        // the sort keeps at most 8 rounds of elements per thread in registers
-        if (strategy == VR_STATIC_SORT || strategy == VR_DYN_SORT)
-            while (nt * 8 < r.max_idx) nt *= 2;
+        while (nt * 2 <= want && nt < 1024) nt *= 2;
+        // the sort keeps at most 8 rounds of elements per thread in registers;
+        // the canonical ranking keeps at most 32 flags per thread in a mask
+        const uint32_t per = (strategy == VR_STATIC_SORT || strategy == VR_DYN_SORT) ? 8u : 32u;
+        while (nt * per < r.max_idx && nt < 1024) nt *= 2;
+        if (nt * per < r.max_idx)
+            return fail(c, VR_ERR_ARG, "batch_tris %u: a unit of %u indices needs more than 1024 threads", batch_tris,
+                        r.max_idx);
         r.nt = nt;
         const uint32_t slots = o.hash_slots ? o.hash_slots : std::max<uint32_t>(8, 1u << log2u(2 * r.max_uniq));
         r.hash_bits = log2u(slots);
@@ -268,7 +274,8 @@ void dispatch_nt(vr_ctx *c, uint32_t nt, const DrawArgs &A, const vr_shader_para
     case 64: launch_dedup<64, MODE, KIND>(c, A, sh, lds, units); break;
     case 128: launch_dedup<128, MODE, KIND>(c, A, sh, lds, units); break;
     case 256: launch_dedup<256, MODE, KIND>(c, A, sh, lds, units); break;
-    default: launch_dedup<512, MODE, KIND>(c, A, sh, lds, units); break;
+    case 512: launch_dedup<512, MODE, KIND>(c, A, sh, lds, units); break;
+    default: launch_dedup<1024, MODE, KIND>(c, A, sh, lds, units); break;
     }
 }
 
@@ -364,6 +371,15 @@ unsigned char *scratch_ptr(int device, std::string *why) {
     return it->second.ptr;
 }
 
+// The aligned check and next() for the primitive-cap class TMC.
+template <uint32_t TMC>
+void launch_plan_first(vr_ctx *c, const PlanArgs &P, uint32_t K, uint32_t *d_plan) {
+    using W = NextClass<TMC>;
+    hipLaunchKernelGGL(k_plan_check<TMC>, dim3(K), dim3(CheckClass<TMC>::threads), 0, c->stream, P, d_plan);
+    hipLaunchKernelGGL(k_plan_next<TMC>, dim3((P.T + W::starts - 1) / W::starts), dim3(W::threads), W::lds,
+                       c->stream, P);
+}
+
 // Builds the plan of a dynamic draw on the context's stream (see vr_plan.h).
 vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, uint32_t nu, uint32_t tmax,
                      uint32_t *d_plan) {
@@ -375,9 +391,11 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     // growing to 8192 so that large draws keep a modest number of segments
     uint32_t L = 2048;
     while (L < 8192 && (uint64_t)L * 2048 < T) L <<= 1;
+    while (L < tmax) L <<= 1;
     const uint32_t nseg = (T + L - 1) / L;
+    const uint32_t fan = plan_fan_in(tmax);
     std::vector<uint32_t> counts{nseg};
-    while (counts.back() > kFanIn) counts.push_back((counts.back() + kFanIn - 1) / kFanIn);
+    while (counts.back() > fan) counts.push_back((counts.back() + fan - 1) / fan);
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t bytes = al(4ull * T) * 2 + al(4ull * nseg);
     std::vector<size_t> tab_off, ent_off;
@@ -410,14 +428,15 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     P.epoch = c->plan_epoch;
     TimedRegion timed(c);
     const uint32_t K = (T + tmax - 1) / tmax;
-    hipLaunchKernelGGL(k_plan_check, dim3(K), dim3(256), 0, c->stream, P, d_plan);
-    if (tmax <= 256)
-        hipLaunchKernelGGL(k_plan_next<256>, dim3((T + kNextBlock - 1) / kNextBlock), dim3(256), 0, c->stream, P);
-    else
-        hipLaunchKernelGGL(k_plan_next<VR_MAX_BATCH_DYNAMIC>, dim3((T + kNextBlock - 1) / kNextBlock), dim3(256), 0,
-                           c->stream, P);
+    switch (plan_class(tmax)) {
+    case 256: launch_plan_first<256>(c, P, K, d_plan); break;
+    case 512: launch_plan_first<512>(c, P, K, d_plan); break;
+    case 1024: launch_plan_first<1024>(c, P, K, d_plan); break;
+    case 2048: launch_plan_first<2048>(c, P, K, d_plan); break;
+    default: launch_plan_first<4096>(c, P, K, d_plan); break;
+    }
     hipLaunchKernelGGL(k_plan_table, dim3(nseg), dim3(256), 4 * L, c->stream, P, tab(0));
-    const uint32_t grp_lds = 2 * kFanIn * tmax;
+    const uint32_t grp_lds = 2 * fan * tmax;
     for (size_t l = 0; l + 1 < counts.size(); ++l)
         hipLaunchKernelGGL(k_plan_compose, dim3(counts[l + 1]), dim3(512), grp_lds, c->stream, tmax, counts[l],
                            (const uint16_t *)tab(l), tab(l + 1), (const uint32_t *)P.fail, P.epoch);
@@ -446,9 +465,9 @@ struct vr_frame {
     void *mem = nullptr;
     DrawDesc *d_draws = nullptr;
     vr_shader_params *d_shaders = nullptr;
-    uint32_t *d_unit_base = nullptr, *d_slot_base = nullptr;
+    uint32_t *d_order = nullptr, *d_unit_base = nullptr, *d_slot_base = nullptr;
     unsigned long long *d_agg = nullptr, *d_dtot = nullptr;
-    uint32_t unit_lds = 0, ballot_stride = 0, lds_total = 0, grid = 1;
+    std::vector<vr::FrameVariant> variants;
     bool index_error = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -456,26 +475,65 @@ struct vr_frame {
 
 namespace {
 
-// The frame kernels: unit bases, the persistent kernel, per-draw counters
-// and (when total_inv is not NULL) the frame's invocation total.
+// The frame kernels: unit bases in variant order, one persistent kernel per
+// variant, per-draw counters and (when total_inv is not NULL) the frame's
+// invocation total.
 struct FrameLaunch {
     const DrawDesc *draws;
+    const uint32_t *order;
     uint32_t n;
     const vr_shader_params *shaders;
     uint32_t *unit_base, *slot_base;
     unsigned long long *agg, *dtot;
-    uint32_t unit_lds, ballot_stride, lds_total, grid;
+    const FrameVariant *variants;
+    uint32_t num_variants;
     uint32_t *err;
     unsigned long long *total_inv;
 };
 
+template <int MODE, int KIND>
+void launch_frame_variant(const FrameLaunch &L, const FrameVariant &v, hipStream_t s) {
+    hipLaunchKernelGGL((k_frame<MODE, KIND>), dim3(v.grid), dim3(kFrameNT), v.lds_total, s, L.draws, L.order, v.lo,
+                       v.hi, L.shaders, (const uint32_t *)L.unit_base, (const uint32_t *)L.slot_base, L.agg,
+                       v.unit_lds, v.ballot_stride, L.err, L.total_inv);
+}
+
+template <int MODE, int KIND>
+int frame_variant_occupancy(uint32_t lds) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_frame<MODE, KIND>, kFrameNT, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu;
+}
+
+// Resident workgroups per CU of a variant's kernel (launch = false), or its
+// launch (launch = true); mode and kind select the instantiation.
+template <int MODE>
+int frame_variant_mode(const FrameLaunch *L, const FrameVariant &v, hipStream_t s, bool launch) {
+    switch (v.kind) {
+    case 0: return launch ? (launch_frame_variant<MODE, 0>(*L, v, s), 0) : frame_variant_occupancy<MODE, 0>(v.lds_total);
+    case 1: return launch ? (launch_frame_variant<MODE, 1>(*L, v, s), 0) : frame_variant_occupancy<MODE, 1>(v.lds_total);
+    default: return launch ? (launch_frame_variant<MODE, 2>(*L, v, s), 0) : frame_variant_occupancy<MODE, 2>(v.lds_total);
+    }
+}
+
+int frame_variant_dispatch(const FrameLaunch *L, const FrameVariant &v, hipStream_t s, bool launch) {
+    switch (v.mode) {
+    case kFrameSort: return frame_variant_mode<kFrameSort>(L, v, s, launch);
+    case kFrameHash: return frame_variant_mode<kFrameHash>(L, v, s, launch);
+    case kFramePHash: return frame_variant_mode<kFramePHash>(L, v, s, launch);
+    case kFrameBallot: return frame_variant_mode<kFrameBallot>(L, v, s, launch);
+    default: return frame_variant_mode<kFrameNaive>(L, v, s, launch);
+    }
+}
+
 void enqueue_frame_kernels(const FrameLaunch &L, hipStream_t s) {
     if (L.n == 0) return;
-    hipLaunchKernelGGL(k_frame_prepare, dim3(1), dim3(1024), 0, s, L.draws, L.n, L.unit_base, L.slot_base, L.err);
-    hipLaunchKernelGGL(k_frame, dim3(L.grid), dim3(kFrameNT), L.lds_total, s, L.draws, L.n, L.shaders,
-                       (const uint32_t *)L.unit_base, (const uint32_t *)L.slot_base, L.agg, L.unit_lds,
-                       L.ballot_stride, L.err, L.total_inv);
-    hipLaunchKernelGGL(k_frame_finish, dim3(L.n), dim3(64), 0, s, L.draws, (const uint32_t *)L.slot_base,
+    hipLaunchKernelGGL(k_frame_prepare, dim3(1), dim3(1024), 0, s, L.draws, L.order, L.n, L.unit_base, L.slot_base,
+                       L.err);
+    for (uint32_t i = 0; i < L.num_variants; ++i) frame_variant_dispatch(&L, L.variants[i], s, true);
+    hipLaunchKernelGGL(k_frame_finish, dim3(L.n), dim3(64), 0, s, L.draws, L.order, (const uint32_t *)L.slot_base,
                        (const unsigned long long *)L.agg, L.dtot);
     if (L.total_inv)
         hipLaunchKernelGGL(k_frame_total, dim3(1), dim3(1024), 0, s, (const unsigned long long *)L.dtot, L.n,
@@ -484,8 +542,9 @@ void enqueue_frame_kernels(const FrameLaunch &L, hipStream_t s) {
 
 void frame_enqueue(vr_frame *f, hipStream_t s) {
     vr_ctx *c = f->c;
-    FrameLaunch L{f->d_draws, f->n, f->d_shaders, f->d_unit_base, f->d_slot_base, f->d_agg, f->d_dtot,
-                  f->unit_lds, f->ballot_stride, f->lds_total, f->grid, &c->d_words->err, &c->d_words->total_inv};
+    FrameLaunch L{f->d_draws, f->d_order, f->n, f->d_shaders, f->d_unit_base, f->d_slot_base, f->d_agg,
+                  f->d_dtot, f->variants.data(), (uint32_t)f->variants.size(), &c->d_words->err,
+                  &c->d_words->total_inv};
     enqueue_frame_kernels(L, s);
 }
 
@@ -508,6 +567,13 @@ struct FrameNeeds {
     bool index_error = false;
     uint32_t lds_total(uint32_t n) const {
         return align16(std::max(unit_lds, 4 * ballot_stride)) + 4 * (n + 1);
+    }
+    void merge(const FrameNeeds &o) {
+        slots += o.slots;
+        units += o.units;
+        unit_lds = std::max(unit_lds, o.unit_lds);
+        ballot_stride = std::max(ballot_stride, o.ballot_stride);
+        index_error = index_error || o.index_error;
     }
 };
 
@@ -562,8 +628,60 @@ vr_status describe_draw(vr_ctx *c, const vr_draw &D, const vr_shader_params &sh,
             need.ballot_stride = std::max(need.ballot_stride, align16(ballot_lds_bytes(D.batch_tris)));
         } else {
             need.units += nb;
-            need.unit_lds = std::max(need.unit_lds, dedup_lds_layout((int)X.mode, r.max_idx, r.max_uniq, r.hash_bits, kFrameNT).total);
+            // the frame kernel runs every unit with kFrameNT threads
+            const uint32_t per = X.mode == kFrameSort ? 8u : 32u;
+            if (r.max_idx > per * kFrameNT)
+                return fail(c, VR_ERR_ARG, "draw %u: batches of %u triangles are too large for a frame", d,
+                            D.batch_tris);
+            need.unit_lds = std::max(need.unit_lds, dedup_lds_layout((int)X.mode, r.max_idx, r.max_uniq, r.hash_bits,
+                                                                     kFrameNT, r.max_uniq).total);
         }
+    }
+    return VR_OK;
+}
+
+// Groups the described draws by variant (dedup mode and vertex program):
+// `order` lists the table positions variant by variant (stable), and every
+// variant gets its kernel's LDS and a grid of at most one chunk of units per
+// workgroup and the CUs' resident workgroups.  VR_ERR_ARG when a variant
+// needs more LDS than a workgroup has.
+vr_status frame_variants(vr_ctx *c, const DrawDesc *desc, const FrameNeeds *needs, uint32_t n,
+                         std::vector<uint32_t> &order, std::vector<FrameVariant> &vars,
+                         std::map<uint64_t, int> *occ_cache) {
+    order.resize(n);
+    for (uint32_t d = 0; d < n; ++d) order[d] = d;
+    auto key = [&](uint32_t d) { return desc[d].mode * 3 + desc[d].kind; };
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
+    vars.clear();
+    for (uint32_t lo = 0; lo < n;) {
+        uint32_t hi = lo + 1;
+        while (hi < n && key(order[hi]) == key(order[lo])) ++hi;
+        FrameNeeds need;
+        for (uint32_t k = lo; k < hi; ++k) need.merge(needs[order[k]]);
+        FrameVariant v{};
+        v.mode = desc[order[lo]].mode;
+        v.kind = desc[order[lo]].kind;
+        v.lo = lo;
+        v.hi = hi;
+        v.ballot_stride = need.ballot_stride;
+        v.unit_lds = align16(std::max(need.unit_lds, 4 * need.ballot_stride));
+        v.lds_total = need.lds_total(hi - lo);
+        if (v.lds_total > c->lds_limit)
+            return fail(c, VR_ERR_ARG, "frame variant needs %u B of LDS per workgroup (limit %zu)", v.lds_total,
+                        c->lds_limit);
+        const uint64_t ck = ((uint64_t)(v.mode * 3 + v.kind) << 32) | v.lds_total;
+        int per_cu;
+        auto it = occ_cache ? occ_cache->find(ck) : std::map<uint64_t, int>::iterator();
+        if (occ_cache && it != occ_cache->end()) {
+            per_cu = it->second;
+        } else {
+            per_cu = frame_variant_dispatch(nullptr, v, nullptr, false);
+            if (occ_cache) (*occ_cache)[ck] = per_cu;
+        }
+        const uint64_t want = std::max<uint64_t>(1, (need.units + kFrameChunk - 1) / kFrameChunk);
+        v.grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)std::max(1, c->num_cus * per_cu));
+        vars.push_back(v);
+        lo = hi;
     }
     return VR_OK;
 }
@@ -632,8 +750,10 @@ vr_status vr_plan_dynamic(vr_ctx *c, const uint32_t *d_indices, uint64_t num_ind
     if (!c) return VR_ERR_ARG;
     if (num_indices % 3 != 0 || num_indices > VR_MAX_INDICES)
         return fail(c, VR_ERR_ARG, "num_indices must be a multiple of 3 below 3*2^30");
-    if (max_unique < 3 || max_unique > VR_MAX_UNIQUE) return fail(c, VR_ERR_ARG, "max_unique outside 3..512");
-    if (max_tris == 0 || max_tris > VR_MAX_BATCH_DYNAMIC) return fail(c, VR_ERR_ARG, "max_tris outside 1..512");
+    if (max_unique < 3 || max_unique > VR_MAX_UNIQUE)
+        return fail(c, VR_ERR_ARG, "max_unique outside 3..%u", (unsigned)VR_MAX_UNIQUE);
+    if (max_tris == 0 || max_tris > VR_MAX_BATCH_DYNAMIC)
+        return fail(c, VR_ERR_ARG, "max_tris outside 1..%u", (unsigned)VR_MAX_BATCH_DYNAMIC);
     const uint64_t T = num_indices / 3;
     if (!d_plan || plan_cap < T + 2) return fail(c, VR_ERR_CAPACITY, "plan buffer must hold T+2 entries");
     if (T && !d_indices) return fail(c, VR_ERR_ARG, "indices are NULL");
@@ -664,6 +784,20 @@ vr_status draw_impl(vr_ctx *c, const uint32_t *d_indices, uint64_t num_indices, 
     if (d_vertices && ((uintptr_t)d_vertices & 15)) return fail(c, VR_ERR_ARG, "vertices must be 16-byte aligned");
     if (out->corners && ((uintptr_t)out->corners & 15)) return fail(c, VR_ERR_ARG, "corners must be 16-byte aligned");
     if (out->verts && ((uintptr_t)out->verts & 15)) return fail(c, VR_ERR_ARG, "verts must be 16-byte aligned");
+    // LDS of the dedup kernels: every unique vertex of a unit is kept when
+    // corners are assembled, else an NT-row stage
+    const int mode = (strategy == VR_STATIC_SORT || strategy == VR_DYN_SORT) ? kSort
+                     : (strategy == VR_DYN_PHASH)                             ? kPHash
+                                                                              : kHash;
+    uint32_t lds = 0;
+    if (strategy != VR_NAIVE && strategy != VR_MULTI && !is_ballot(strategy)) {
+        lds = dedup_lds_layout(mode, r.max_idx, r.max_uniq, r.hash_bits, r.nt, out->corners ? r.max_uniq : r.nt).total;
+        if (lds > c->lds_limit)
+            return fail(c, VR_ERR_ARG,
+                        "LDS need %u B exceeds the %zu B limit (lower max_unique, batch_tris or hash_slots, or "
+                        "request indexed outputs only)",
+                        lds, c->lds_limit);
+    }
     unsigned char *fixed = nullptr;   // the static scratch array on this device (noalloc)
     if (noalloc) {
         if (is_dynamic(strategy) && T && !(opts && opts->d_plan))
@@ -785,13 +919,6 @@ vr_status draw_impl(vr_ctx *c, const uint32_t *d_indices, uint64_t num_indices, 
         else if (sh.kind == 1) launch_ballot<1>(c, A, sh, lds, nb_bound);
         else launch_ballot<2>(c, A, sh, lds, nb_bound);
     } else {
-        const int mode = (strategy == VR_STATIC_SORT || strategy == VR_DYN_SORT) ? kSort
-                         : (strategy == VR_DYN_PHASH)                             ? kPHash
-                                                                                  : kHash;
-        const uint32_t lds = dedup_lds_layout(mode, r.max_idx, r.max_uniq, r.hash_bits, r.nt).total;
-        if (lds > c->lds_limit)
-            return fail(c, VR_ERR_ARG, "LDS need %u B exceeds the %zu B limit (lower hash_slots or batch_tris)", lds,
-                        c->lds_limit);
         if (mode == kSort) dispatch_kind<kSort>(c, sh.kind, r.nt, A, sh, lds, nb_bound);
         else if (mode == kHash) dispatch_kind<kHash>(c, sh.kind, r.nt, A, sh, lds, nb_bound);
         else dispatch_kind<kPHash>(c, sh.kind, r.nt, A, sh, lds, nb_bound);
@@ -1044,31 +1171,31 @@ vr_status vr_frame_create(vr_ctx *c, const vr_draw *draws, uint32_t n, const vr_
     if (n > VR_MAX_FRAME_DRAWS) return fail(c, VR_ERR_ARG, "a frame holds at most %d draws", VR_MAX_FRAME_DRAWS);
     if (n && (!draws || !shaders || ns == 0)) return fail(c, VR_ERR_ARG, "draws and shaders must not be NULL");
     std::vector<DrawDesc> desc(n);
+    std::vector<FrameNeeds> needs(n);
     FrameNeeds need;
     for (uint32_t d = 0; d < n; ++d) {
         if (draws[d].shader >= ns) return fail(c, VR_ERR_ARG, "draw %u: shader %u out of range", d, draws[d].shader);
-        vr_status st = describe_draw(c, draws[d], shaders[draws[d].shader], d, desc[d], need);
+        vr_status st = describe_draw(c, draws[d], shaders[draws[d].shader], d, desc[d], needs[d]);
         if (st != VR_OK) return st;
+        need.merge(needs[d]);
     }
-    const uint32_t unit_lds = align16(std::max(need.unit_lds, 4 * need.ballot_stride));
-    const uint32_t ballot_stride = need.ballot_stride, lds_total = need.lds_total(n);
+    DeviceGuard g(c->device);
+    std::vector<uint32_t> order;
+    std::vector<FrameVariant> vars;
+    vr_status vst = frame_variants(c, desc.data(), needs.data(), n, order, vars, nullptr);
+    if (vst != VR_OK) return vst;
     const uint64_t slots = need.slots;
     const bool index_error = need.index_error;
-    if (lds_total > c->lds_limit)
-        return fail(c, VR_ERR_ARG, "frame needs %u B of LDS per workgroup (limit %zu)", lds_total, c->lds_limit);
 
-    DeviceGuard g(c->device);
     vr_frame *f = new vr_frame();
     f->c = c;
     f->n = n;
-    f->unit_lds = unit_lds;
-    f->ballot_stride = ballot_stride;
-    f->lds_total = lds_total;
+    f->variants = vars;
     f->index_error = index_error;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t o_draws = 0, o_sh = al(sizeof(DrawDesc) * n), o_ub = o_sh + al(sizeof(vr_shader_params) * ns),
-                 o_sb = o_ub + al(4ull * (n + 1)), o_agg = o_sb + al(4ull * (n + 1)), o_dt = o_agg + al(8 * (slots + 1)),
-                 total = o_dt + al(8ull * (n + 1));
+    const size_t o_draws = 0, o_sh = al(sizeof(DrawDesc) * n), o_ord = o_sh + al(sizeof(vr_shader_params) * ns),
+                 o_ub = o_ord + al(4ull * n), o_sb = o_ub + al(4ull * (n + 1)), o_agg = o_sb + al(4ull * (n + 1)),
+                 o_dt = o_agg + al(8 * (slots + 1)), total = o_dt + al(8ull * (n + 1));
     if (hipMalloc(&f->mem, total) != hipSuccess) {
         delete f;
         return fail(c, VR_ERR_OOM, "frame allocation of %zu bytes failed", total);
@@ -1076,6 +1203,7 @@ vr_status vr_frame_create(vr_ctx *c, const vr_draw *draws, uint32_t n, const vr_
     unsigned char *m = (unsigned char *)f->mem;
     f->d_draws = (DrawDesc *)(m + o_draws);
     f->d_shaders = (vr_shader_params *)(m + o_sh);
+    f->d_order = (uint32_t *)(m + o_ord);
     f->d_unit_base = (uint32_t *)(m + o_ub);
     f->d_slot_base = (uint32_t *)(m + o_sb);
     f->d_agg = (unsigned long long *)(m + o_agg);
@@ -1083,11 +1211,7 @@ vr_status vr_frame_create(vr_ctx *c, const vr_draw *draws, uint32_t n, const vr_
     hipError_t e = hipSuccess;
     if (n) e = hipMemcpy(f->d_draws, desc.data(), sizeof(DrawDesc) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess && n) e = hipMemcpy(f->d_shaders, shaders, sizeof(vr_shader_params) * ns, hipMemcpyHostToDevice);
-    int per_cu = 0;
-    if (e == hipSuccess &&
-        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_frame, kFrameNT, lds_total) != hipSuccess || per_cu < 1))
-        per_cu = 1;
-    f->grid = (uint32_t)std::max(1, c->num_cus * per_cu);
+    if (e == hipSuccess && n) e = hipMemcpy(f->d_order, order.data(), 4ull * n, hipMemcpyHostToDevice);
     if (e == hipSuccess && capture_graph && n) {
         hipStream_t cs = nullptr;
         e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -1304,11 +1428,12 @@ struct ServerReq {
 // uploaded (draw table, shader table, zeroed words), [words, end) is read
 // back (error word and per-draw counters); bases and totals follow.
 struct TickLayout {
-    size_t sh, words, cnt, end, ubase, sbase, dtot, total;
+    size_t sh, ord, words, cnt, end, ubase, sbase, dtot, total;
     explicit TickLayout(uint32_t n) {
         auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
         sh = al(sizeof(DrawDesc) * n);
-        words = sh + al(sizeof(vr_shader_params) * n);
+        ord = sh + al(sizeof(vr_shader_params) * n);
+        words = ord + al(4ull * n);
         cnt = words + 256;
         end = cnt + al(32ull * n);
         ubase = end;
@@ -1340,7 +1465,7 @@ struct vr_server {
     unsigned char *arena = nullptr;
     uint32_t *d_word = nullptr;
     std::vector<TickSlot> slots;
-    std::map<uint32_t, int> per_cu;   // LDS bytes -> resident frame workgroups per CU
+    std::map<uint64_t, int> per_cu;   // (variant, LDS bytes) -> resident frame workgroups per CU
     std::mutex m;
     std::condition_variable cv_work, cv_done;
     sched::Scheduler *sch = nullptr;
@@ -1386,16 +1511,6 @@ uint32_t *server_plan(vr_server *s, ServerMesh &M, uint32_t nu, uint32_t bt) {
     return plan;
 }
 
-int server_occupancy(vr_server *s, uint32_t lds) {
-    auto it = s->per_cu.find(lds);
-    if (it != s->per_cu.end()) return it->second;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_frame, kFrameNT, lds) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    s->per_cu[lds] = per_cu;
-    return per_cu;
-}
-
 // Enqueues one tick over `jobs` (lock held).  A job that cannot be described
 // is finished with its error and processed as an empty draw.
 vr_status server_launch(vr_server *s, uint32_t tick, const std::vector<uint64_t> &jobs) {
@@ -1408,6 +1523,7 @@ vr_status server_launch(vr_server *s, uint32_t tick, const std::vector<uint64_t>
     memset(S.host + L.words, 0, 256);
     unsigned long long *dcnt = (unsigned long long *)(S.dev + L.cnt);
     FrameNeeds need;
+    std::vector<FrameNeeds> needs(n);
     for (uint32_t d = 0; d < n; ++d) {
         sched::Job *j = s->sch->find(jobs[d]);
         const ServerReq &R = s->reqs[jobs[d]];
@@ -1431,13 +1547,20 @@ vr_status server_launch(vr_server *s, uint32_t tick, const std::vector<uint64_t>
                 D.num_indices = 0;
             }
         }
-        if (describe_draw(c, D, hs[d], d, hd[d], need) != VR_OK) {
+        if (describe_draw(c, D, hs[d], d, hd[d], needs[d]) != VR_OK) {
             if (j->status == VR_OK) j->status = VR_ERR_ARG;
             D.num_indices = 0;
             D.d_plan = nullptr;
-            if (describe_draw(c, D, hs[d], d, hd[d], need) != VR_OK) return VR_ERR_ARG;
+            needs[d] = FrameNeeds();
+            if (describe_draw(c, D, hs[d], d, hd[d], needs[d]) != VR_OK) return VR_ERR_ARG;
         }
+        need.merge(needs[d]);
     }
+    std::vector<uint32_t> order;
+    std::vector<FrameVariant> vars;
+    if (frame_variants(c, hd, needs.data(), n, order, vars, &s->per_cu) != VR_OK)
+        return server_fail(s, VR_ERR_ARG, "%s", c->error.c_str());
+    if (n) memcpy(S.host + L.ord, order.data(), 4ull * n);
     if (need.slots + 1 > S.agg_cap) {
         if (S.agg) (void)hipFree(S.agg);
         S.agg = nullptr;
@@ -1447,14 +1570,11 @@ vr_status server_launch(vr_server *s, uint32_t tick, const std::vector<uint64_t>
             return server_fail(s, VR_ERR_OOM, "tick aggregates: out of memory");
         }
     }
-    const uint32_t lds_total = need.lds_total(n);
-    const uint64_t want = std::max<uint64_t>(1, (need.units + kFrameChunk - 1) / kFrameChunk);
-    const uint64_t full = (uint64_t)c->num_cus * server_occupancy(s, lds_total);
     CtxWords *dw = (CtxWords *)(S.dev + L.words);
-    FrameLaunch F{(const DrawDesc *)S.dev, n, (const vr_shader_params *)(S.dev + L.sh),
-                  (uint32_t *)(S.dev + L.ubase), (uint32_t *)(S.dev + L.sbase), S.agg,
-                  (unsigned long long *)(S.dev + L.dtot), align16(std::max(need.unit_lds, 4 * need.ballot_stride)),
-                  need.ballot_stride, lds_total, (uint32_t)std::min(want, full), &dw->err, &dw->total_inv};
+    FrameLaunch F{(const DrawDesc *)S.dev, (const uint32_t *)(S.dev + L.ord), n,
+                  (const vr_shader_params *)(S.dev + L.sh), (uint32_t *)(S.dev + L.ubase),
+                  (uint32_t *)(S.dev + L.sbase), S.agg, (unsigned long long *)(S.dev + L.dtot), vars.data(),
+                  (uint32_t)vars.size(), &dw->err, &dw->total_inv};
     S.n = n;
     hipError_t e = hipMemcpyAsync(S.dev, S.host, L.cnt, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) {

@@ -27,7 +27,8 @@ STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 DYNAMIC = (VR_DYN_SORT, VR_DYN_HASH, VR_DYN_PHASH, VR_DYN_BALLOT)
 OUT_FLOATS = 12
 # limits of include/vr.h
-VR_MAX_BATCH_STATIC, VR_MAX_BATCH_BALLOT, VR_MAX_BATCH_DYNAMIC, VR_MAX_UNIQUE = 256, 1024, 512, 512
+VR_MAX_BATCH_STATIC, VR_MAX_BATCH_BALLOT, VR_MAX_BATCH_DYNAMIC, VR_MAX_UNIQUE = 256, 1024, 4096, 4096
+VR_MAX_HASH_SLOTS = 8192
 
 EXPORTS = ["vr_create", "vr_destroy", "vr_set_stream", "vr_check_args", "vr_plan_dynamic", "vr_process_draw",
            "vr_process_draw_noalloc",

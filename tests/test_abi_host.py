@@ -53,9 +53,12 @@ def _cases():
     yield "static_cap", dict(n=300, strategy=vr.VR_STATIC_HASH, bt=257)
     yield "ballot_cap_ok", dict(n=300, strategy=vr.VR_STATIC_BALLOT, bt=1024)
     yield "ballot_cap", dict(n=300, strategy=vr.VR_STATIC_BALLOT, bt=1025)
-    yield "dyn_cap", dict(n=300, strategy=vr.VR_DYN_BALLOT, bt=513)
+    yield "dyn_cap", dict(n=300, strategy=vr.VR_DYN_BALLOT, bt=4097)
+    yield "dyn_cap_ok", dict(n=300, strategy=vr.VR_DYN_HASH, bt=4096, nu=4096)
     yield "nu2", dict(n=300, strategy=vr.VR_DYN_SORT, bt=64, nu=2)
-    yield "nu513", dict(n=300, strategy=vr.VR_DYN_SORT, bt=64, nu=513)
+    yield "nu4097", dict(n=300, strategy=vr.VR_DYN_SORT, bt=64, nu=4097)
+    yield "slots_big", dict(n=300, strategy=vr.VR_DYN_HASH, bt=64, nu=64, slots=16384)
+    yield "slots_big_ok", dict(n=300, strategy=vr.VR_DYN_HASH, bt=64, nu=64, slots=8192)
     yield "nu_ignored_static", dict(n=300, strategy=vr.VR_STATIC_SORT, bt=64, nu=2)
     yield "wg_bad", dict(n=300, strategy=vr.VR_DYN_SORT, bt=64, wg=100)
     yield "wg_ok", dict(n=300, strategy=vr.VR_DYN_SORT, bt=64, wg=192)
@@ -98,3 +101,11 @@ def test_null_context_is_an_argument_error():
     assert vr.lib().vr_sync(None, None) == vr.VR_ERR_ARG
     assert vr.lib().vr_set_stream(None, None) == vr.VR_ERR_ARG
     assert vr.lib().vr_math_selftest(None, 0, 0, 1, None, None) == vr.VR_ERR_ARG
+
+
+def test_binding_limits_match_header():
+    text = open(os.path.join(ROOT, "include", "vr.h")).read()
+    defs = dict(re.findall(r"#define (VR_MAX_[A-Z_]+)\s+(\d+)", text))
+    for name in ("VR_MAX_BATCH_STATIC", "VR_MAX_BATCH_BALLOT", "VR_MAX_BATCH_DYNAMIC", "VR_MAX_UNIQUE",
+                 "VR_MAX_HASH_SLOTS"):
+        assert getattr(vr, name) == int(defs[name]), name

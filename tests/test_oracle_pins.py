@@ -254,7 +254,7 @@ def test_argument_errors():
     assert vro.process_draw(idx, v, sp, vro.STATIC_SORT, 0)[0] == vro.ERR_ARG        # batch 0
     assert vro.process_draw(idx, v, sp, vro.STATIC_SORT, 257)[0] == vro.ERR_ARG      # batch cap
     assert vro.process_draw(idx, v, sp, vro.DYN_HASH, 64, {"max_unique": 2})[0] == vro.ERR_ARG
-    assert vro.process_draw(idx, v, sp, vro.DYN_HASH, 64, {"max_unique": 513})[0] == vro.ERR_ARG
+    assert vro.process_draw(idx, v, sp, vro.DYN_HASH, 64, {"max_unique": 4097})[0] == vro.ERR_ARG
     assert vro.process_draw(idx, v, sp, vro.DYN_HASH, 64, {"hash_slots": 100})[0] == vro.ERR_ARG
     sp.num_lights = 17
     assert vro.process_draw(idx, v, sp, vro.NAIVE, 1)[0] == vro.ERR_ARG
