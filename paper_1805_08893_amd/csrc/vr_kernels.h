@@ -35,6 +35,7 @@ struct DrawArgs {
     uint32_t max_uniq;          // LDS capacity in shaded vertices
     uint32_t need_prefix;       // tris / verts / unit arrays requested
     uint32_t status_cap;        // look-back words available
+    uint32_t stream_verts;      // no corners: shaded vertices stream out through an NT-row stage
 };
 
 // Units a launch may take: the plan's count, bounded by the look-back
@@ -495,8 +496,9 @@ __device__ __forceinline__ const uint16_t *radix_passes(const uint32_t *s_keys, 
 template <int NT, int MODE, int KIND>
 __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_params &sh, uint32_t u, uint32_t nb,
                                            unsigned char *smem) {
-    // without corners the shaded vertices stream out through an NT-row stage
-    const bool stream = A.corners == nullptr;
+    // without corners, units whose unique vertices would not leave room for
+    // several workgroups per CU stream them out through an NT-row stage
+    const bool stream = A.stream_verts != 0;
     const DedupLds L = dedup_lds_layout(MODE, A.max_idx, A.max_uniq, A.hash_bits, NT, stream ? NT : A.max_uniq);
     uint32_t *s_keys = (uint32_t *)(smem + L.keys);
     uint16_t *s_local = (uint16_t *)(smem + L.local);

@@ -790,8 +790,15 @@ vr_status draw_impl(vr_ctx *c, const uint32_t *d_indices, uint64_t num_indices, 
                      : (strategy == VR_DYN_PHASH)                             ? kPHash
                                                                               : kHash;
     uint32_t lds = 0;
+    bool stream = false;
     if (strategy != VR_NAIVE && strategy != VR_MULTI && !is_ballot(strategy)) {
-        lds = dedup_lds_layout(mode, r.max_idx, r.max_uniq, r.hash_bits, r.nt, out->corners ? r.max_uniq : r.nt).total;
+        lds = dedup_lds_layout(mode, r.max_idx, r.max_uniq, r.hash_bits, r.nt, r.max_uniq).total;
+        // indexed outputs only: shaded vertices stream out when keeping them all
+        // would leave room for fewer than three workgroups per CU
+        if (!out->corners && 3 * lds > c->lds_limit) {
+            stream = true;
+            lds = dedup_lds_layout(mode, r.max_idx, r.max_uniq, r.hash_bits, r.nt, r.nt).total;
+        }
         if (lds > c->lds_limit)
             return fail(c, VR_ERR_ARG,
                         "LDS need %u B exceeds the %zu B limit (lower max_unique, batch_tris or hash_slots, or "
@@ -847,6 +854,7 @@ vr_status draw_impl(vr_ctx *c, const uint32_t *d_indices, uint64_t num_indices, 
     A.max_idx = r.max_idx;
     A.max_uniq = r.max_uniq;
     A.need_prefix = (out->tris || out->verts || out->unit_offsets || out->unit_invocations) ? 1u : 0u;
+    A.stream_verts = stream ? 1u : 0u;
 
     const vr_shader_params &sh = *shader;
     if (strategy == VR_MULTI) {
