@@ -171,10 +171,22 @@ def scene_benchmark(stage, seed=3, num_draws=2000, replays=10):
         vr.vr_frame_destroy(frame)
     classes = {k: {"strategy": vr.STRATEGY_NAMES[v["strategy"]], "batch_tris": v["batch_tris"],
                    "max_unique": v["max_unique"]} for k, v in tuner.table.items()}
+    # roofs of the frame: per draw 12 B/triangle of indices, 32 B per
+    # referenced vertex, 144 B/triangle of corners; FP32 work = invocations x
+    # the program's operations
+    inv_d = counters[:, 0].cpu().numpy()
+    alg_bytes = alg_flops = 0
+    for d in range(num_draws):
+        m = bases[which[d]]
+        T = int(min(Ts[d], m.num_tris))
+        alg_bytes += 156 * T + 32 * len(np.unique(m.indices[:3 * T]))
+        alg_flops += int(inv_d[d]) * shader_flops(shaders[shade[d]])
     return {"draws": num_draws, "triangles": total_T, "frame_ms": frame_ms, "per_draw_launch_ms": loop_ms,
             "frame_tri_per_s": total_T / (frame_ms * 1e-3), "per_draw_tri_per_s": total_T / (loop_ms * 1e-3),
             "speedup_frame_vs_per_draw": loop_ms / frame_ms, "invocations_frame": inv_frame,
-            "invocations_per_draw": inv_loop, "autotune_and_plan_s": t_tune, "classes": classes}
+            "invocations_per_draw": inv_loop, "autotune_and_plan_s": t_tune,
+            "algorithmic_bytes": alg_bytes, "hbm_frac": alg_bytes / (frame_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "alu_frac": alg_flops / (frame_ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, "classes": classes}
 
 
 def sweep(mesh, sp, reps=10):
@@ -624,13 +636,17 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+RATE_SWEEP = (4000.0, 16000.0, 64000.0)
+
+
 def serving_benchmark(stage, seed=11, n=2000, rate=500.0, budget=64 << 30, small_budget=256 << 20):
     """A Poisson stream of draw requests against 200 resident meshes (sizes
     log-normal around 20k triangles, clamped to [1k, 2M]; a request draws a
     whole mesh with Phong lighting of 1..16 lights), served by the
     continuous-batching server and by the same server launching every
-    request alone; a burst of the same requests for peak throughput; and the
-    stream again under a 256 MB result budget (queueing and rejections)."""
+    request alone, at 500 requests/s and at the higher rates of RATE_SWEEP;
+    a burst of the same requests for peak throughput; and the stream again
+    under a 256 MB result budget (queueing and rejections)."""
     import torch
     from paper_1805_08893_amd import vr, serve
     from paper_1805_08893_amd import workloads as W
@@ -683,6 +699,16 @@ def serving_benchmark(stage, seed=11, n=2000, rate=500.0, budget=64 << 30, small
             got, late, wall = serve.replay(srv, reqs, tr["arrival"])
             out = serve.summarize(got, wall)
             out["submit_late_ms_p99"] = float(np.percentile(late, 99) * 1e3)
+            # the same stream at higher mean rates (arrival times scaled), up to
+            # past what one launch per request sustains
+            sweep = []
+            for r in RATE_SWEEP:
+                got, late, wall = serve.replay(srv, reqs, tr["arrival"] * (rate / r))
+                sv = serve.summarize(got, wall)
+                sweep.append({"rate_req_per_s": r, **{k: sv[k] for k in (
+                    "tri_per_s", "req_per_s", "latency_ms_p50", "latency_ms_p99", "requests_per_tick")},
+                    "submit_late_ms_p99": float(np.percentile(late, 99) * 1e3)})
+            out["rate_sweep"] = sweep
             out["burst_tri_per_s"] = burst["tri_per_s"]
             out["burst_wall_s"] = burst["wall_s"]
             out["burst_requests_per_tick"] = burst["requests_per_tick"]

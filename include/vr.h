@@ -352,8 +352,8 @@ vr_status vr_process_draws(vr_ctx *ctx, const vr_draw *draws, uint32_t num_draws
  * paper picks its batch sizes by such a search, Sections 4.2 and 5).  For
  * every candidate the draw is processed with per-corner output into context
  * scratch: the plan is built (timed as plan_ms) for dynamic strategies, one
- * untimed warm-up, then `reps` timed draws (kernel_ms = mean time of the main
- * kernel).  Invalid candidates get kernel_ms = -1.  *best receives the index
+ * untimed warm-up, then `reps` timed draws (kernel_ms = the fastest of them,
+ * main kernel only: the repetition least disturbed by other device work).  Invalid candidates get kernel_ms = -1.  *best receives the index
  * of the fastest valid candidate by kernel_ms.  Synchronous; allocates
  * scratch as needed.
  */

@@ -50,7 +50,7 @@ def _lib():
     return L
 
 
-def vr_autotune(ctx, indices, vertices, shader, candidates=DEFAULT_CANDIDATES, reps=3):
+def vr_autotune(ctx, indices, vertices, shader, candidates=DEFAULT_CANDIDATES, reps=5):
     """Times every candidate on this draw; returns (best index, list of dicts)."""
     sh = shader if isinstance(shader, vr.vr_shader_params) else vr.make_shader(shader)
     arr = (vr_tune_candidate * len(candidates))(*[vr_tune_candidate(s, bt, nu, 0, 0.0, 0.0, 0)

@@ -10,7 +10,7 @@
 // order, so every variant owns one contiguous range of units.  One persistent
 // kernel per variant, compiled for that variant alone (so its registers and
 // LDS are those of the variant, not of the widest one), deals its range out
-// to its workgroups in chunks of kFrameChunk units, round robin, finds each
+// to its workgroups in chunks of frame_chunk(mode) units, round robin, finds each
 // unit's draw by binary search in an LDS copy of the range's draw bases, and
 // runs the single-draw device function.  Per-unit aggregates are reduced per
 // draw afterwards, so no same-address atomics are on the hot path.
@@ -22,7 +22,9 @@ namespace vr {
 
 enum FrameMode : uint32_t { kFrameSort = 0, kFrameHash = 1, kFramePHash = 2, kFrameBallot = 3, kFrameNaive = 4 };
 constexpr uint32_t kFrameNT = 256;
-constexpr uint32_t kFrameChunk = 4;      // consecutive units a workgroup takes at a time
+// Consecutive units a workgroup takes at a time: 4, or 16 naive chunks of 256
+// corners (small units, whose draw lookup would otherwise weigh).
+__host__ __device__ constexpr uint32_t frame_chunk(uint32_t mode) { return mode == kFrameNaive ? 16u : 4u; }
 constexpr uint32_t kFrameMaxDraws = 4096;
 
 // One persistent launch of a frame: the draws of one variant (order
@@ -169,7 +171,12 @@ __global__ __launch_bounds__(kFrameNT) void k_frame(const DrawDesc *draws, const
     __syncthreads();
     const uint32_t U = s_base[m];
     const uint32_t G = gridDim.x;
-    for (uint32_t c0 = s_base[0] + blockIdx.x * kFrameChunk; c0 < U; c0 += G * kFrameChunk) {
+    constexpr uint32_t kChunk = frame_chunk(MODE);
+    uint32_t kd = 0xFFFFFFFFu;   // the draw whose descriptor is loaded
+    DrawArgs A{};
+    const vr_shader_params *sh = shaders;
+    uint32_t nb = 0;
+    for (uint32_t c0 = s_base[0] + blockIdx.x * kChunk; c0 < U; c0 += G * kChunk) {
         // the draw of unit c0: largest k with s_base[k] <= c0
         uint32_t a = 0, b = m;   // invariant: s_base[a] <= c0 < s_base[b]
         while (b - a > 1) {
@@ -178,12 +185,16 @@ __global__ __launch_bounds__(kFrameNT) void k_frame(const DrawDesc *draws, const
             else b = mid;
         }
         uint32_t k = a;
-        for (uint32_t u = c0; u < min(U, c0 + kFrameChunk); ++u) {
+        for (uint32_t u = c0; u < min(U, c0 + kChunk); ++u) {
             while (u >= s_base[k + 1]) ++k;   // units of empty draws are skipped
-            const DrawDesc D = draws[order[lo + k]];
-            const DrawArgs A = frame_args(D, agg + slot_base[lo + k], err, total_inv);
-            const uint32_t nb = slot_base[lo + k + 1] - slot_base[lo + k];
-            frame_unit<MODE, KIND>(A, shaders[D.shader], u - s_base[k], nb, smem, ballot_stride);
+            if (k != kd) {   // descriptors are loaded once per draw, not per unit
+                kd = k;
+                const DrawDesc D = draws[order[lo + k]];
+                A = frame_args(D, agg + slot_base[lo + k], err, total_inv);
+                sh = shaders + D.shader;
+                nb = slot_base[lo + k + 1] - slot_base[lo + k];
+            }
+            frame_unit<MODE, KIND>(A, *sh, u - s_base[k], nb, smem, ballot_stride);
         }
     }
 }

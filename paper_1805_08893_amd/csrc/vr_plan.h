@@ -23,10 +23,11 @@
 //     table gives the exit offset at the segment's end (one lane per entry
 //     follows next() in LDS); tables of consecutive ranges are composed into
 //     one, level by level, until few remain.
-//  3. Resolution (k_plan_top, k_plan_resolve, k_plan_emit, k_plan_pack).  The
-//     top tables are applied in order from entry 0, entries are pushed down
-//     the levels, every segment walks next() from its entry to list its batch
-//     starts, and the lists are packed into [B, start_0, .., start_{B-1}, T].
+//  3. Resolution (k_plan_top, k_plan_resolve, k_plan_emit).  The top tables
+//     are applied in order from entry 0 and entries are pushed down the
+//     levels; at level 0 every segment takes its entry, walks next() from it
+//     to list its batch starts, and copies them into [B, start_0, ..,
+//     start_{B-1}, T] at an offset found by a decoupled look-back.
 // Every step does bounded parallel work whatever the batch structure; the
 // result equals the sequential chain exactly.
 #pragma once
@@ -59,11 +60,11 @@ __host__ __device__ inline uint32_t plan_fan_in(uint32_t tmax) {
 // power-of-two hash table at most 8/9 full.
 template <uint32_t TMC>
 struct NextClass {
-    static constexpr uint32_t threads = TMC <= 1024 ? 256 : 512;
+    static constexpr uint32_t threads = TMC == 1024 ? 256 : 512;
     static constexpr uint32_t starts = threads;
     static constexpr uint32_t tris = starts + TMC;
     static constexpr uint32_t corners = 3 * tris;
-    static constexpr uint32_t per = corners / threads;
+    static constexpr uint32_t per = (corners + threads - 1) / threads;
     static constexpr uint32_t bits = ceil_log2(corners + corners / 8);
     static constexpr uint32_t slots = 1u << bits;
     // LDS: keys -> corner positions grouped by slot (+ the difference array),
@@ -71,7 +72,7 @@ struct NextClass {
     // occurrences packed per triangle (three 16-bit positions in 64 bits)
     static constexpr uint32_t prev_words = (slots / 4 > tris + 4) ? slots / 4 : tris + 4;
     static constexpr uint32_t lds = 4 * corners + 4 * slots + 8 * prev_words + 64;
-    static_assert(corners % threads == 0, "corners split evenly over the threads");
+    static_assert(slots % threads == 0, "table slots split evenly over the threads");
     static_assert(slots >= corners + corners / 8 && corners < kNone, "window fits the table and 16-bit positions");
     static_assert(2 * corners + 4 * (starts + 1) <= 4 * corners, "difference array fits behind the positions");
     static_assert(lds <= 160 * 1024, "window fits the LDS");
@@ -314,15 +315,22 @@ __global__ __launch_bounds__(NextClass<TMC>::threads) void k_plan_next(PlanArgs 
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
         const uint32_t i = tid + NT * k;
+        uint32_t lo = 1, hi = 0;
         if (i < n) {
             ((uint16_t *)s_prev)[4 * (i / 3) + i % 3] = (uint16_t)best[k];
             const uint32_t lo_prev = best[k] == kNone ? 0u : best[k] / 3 + 1;
             const uint32_t lo_win = i + 1 > span ? (i + 1 - span + 2) / 3 : 0u;
-            const uint32_t lo = max(lo_prev, lo_win), hi = min(i / 3, kNextBlock - 1);
-            if (lo <= hi) {
-                atomicAdd(&s_diff[lo], 1);
-                atomicAdd(&s_diff[hi + 1], -1);
-            }
+            lo = max(lo_prev, lo_win);
+            hi = min(i / 3, kNextBlock - 1);
+        }
+        // many corners start at 0 (no earlier occurrence in the first window):
+        // one atomic per wavefront for them; ends past the last start are
+        // never read and are dropped
+        const uint64_t at0 = ballot(lo == 0 && lo <= hi);
+        if (at0 && lane_id() == (uint32_t)__builtin_ctzll(at0)) atomicAdd(&s_diff[0], (int)__popcll(at0));
+        if (lo <= hi) {
+            if (lo != 0) atomicAdd(&s_diff[lo], 1);
+            if (hi + 1 < kNextBlock) atomicAdd(&s_diff[hi + 1], -1);
         }
     }
     __syncthreads();
@@ -476,79 +484,88 @@ __global__ __launch_bounds__(256) void k_plan_resolve(uint32_t tmax, uint32_t co
     }
 }
 
-// Every segment lists its batch starts: from its entry, follow next().
-__global__ __launch_bounds__(64) void k_plan_emit(PlanArgs P, const uint16_t *entry, uint32_t *cuts,
-                                                  uint32_t *ncuts) {
-    extern __shared__ uint32_t s_next[];   // seg_len entries
-    if (plan_is_aligned(P.fail, P.epoch)) return;
-    const uint32_t s = blockIdx.x;
-    const uint32_t b = seg_lo(P, s), e = seg_hi(P, s);
-    for (uint32_t i = threadIdx.x; i < e - b; i += 64) s_next[i] = P.next[b + i];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t off = entry[s];
-        uint32_t n = 0;
-        if (off != kEnd) {
-            for (uint32_t x = b + off; x < e; x = s_next[x - b]) cuts[b + n++] = x;
+// Level 0, merged with listing and packing.  Segment s receives its entry:
+// directly from `up` when the tables have one level, else its group's entry
+// at level 1 pushed through the tables of the group's earlier segments
+// (staged in LDS).  One thread follows next() from the entry (next() of the
+// segment staged in LDS) and lists the segment's batch starts; the segment
+// publishes its count and resolves its offset in the plan with a decoupled
+// look-back over the segments, then the block copies its starts there.  The
+// status words hold [63:32] the call's epoch, [31:30] a flag (1 count, 2
+// prefix including the segment), [29:0] the count, so words left by earlier
+// calls read as not ready and nothing needs clearing.  The last segment
+// writes B and T.
+__device__ __forceinline__ uint32_t plan_lookback(unsigned long long *status, uint32_t s, uint32_t cnt,
+                                                  uint32_t epoch, uint32_t *err) {
+    const uint32_t lane = lane_id();
+    const unsigned long long tag = (unsigned long long)epoch << 32;
+    uint32_t excl = 0;
+    int64_t hi = (int64_t)s;   // the window is segments hi - 64 .. hi - 1, lane i reading hi - 1 - i
+    uint32_t spins = 0;
+    while (hi > 0) {
+        const int64_t j = hi - 1 - (int64_t)lane;
+        const unsigned long long w =
+            j >= 0 ? __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : (tag | (2u << 30));
+        const uint32_t flag = (w >> 32) == epoch ? (uint32_t)(w >> 30) & 3u : 0u;
+        const uint64_t inc = ballot(flag == 2);
+        const uint64_t need = inc ? ((inc & (~inc + 1)) << 1) - 1 : ~0ull;
+        if (ballot(flag == 0) & need) {
+            if (++spins > (1u << 26)) {
+                if (lane == 0) raise_error(err, VR_ERR_DEVICE);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
         }
-        ncuts[s] = n;
+        const uint32_t v = ((need >> lane) & 1ull) ? (uint32_t)w & 0x3FFFFFFFu : 0u;
+        excl += (uint32_t)__builtin_amdgcn_readlane(wave_incl_scan(v), kWave - 1);
+        if (inc) break;
+        hi -= kWave;
     }
+    if (lane == 0)
+        __hip_atomic_store(&status[s], tag | (2ull << 30) | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
 }
 
-// Packing with one workgroup per segment (draws of at most kPackSegs
-// segments): a segment's offset is the sum of the counts before it, read
-// coalesced; the last segment also writes B and T.
-constexpr uint32_t kPackSegs = 4096;
-
-__global__ __launch_bounds__(64) void k_plan_pack_seg(PlanArgs P, const uint32_t *cuts, const uint32_t *ncuts,
-                                                      uint32_t *plan) {
+__global__ __launch_bounds__(256) void k_plan_emit(PlanArgs P, const uint16_t *tab0, const uint16_t *up,
+                                                   uint32_t direct, unsigned long long *status, uint32_t *plan) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ uint32_t s_cnt, s_off;
     if (plan_is_aligned(P.fail, P.epoch)) return;
-    const uint32_t s = blockIdx.x;
-    uint32_t sum = 0;
-    for (uint32_t j = lane_id(); j < s; j += kWave) sum += ncuts[j];
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) sum += __shfl_xor(sum, d, kWave);
-    const uint32_t b = seg_lo(P, s), cnt = ncuts[s];
-    for (uint32_t i = lane_id(); i < cnt; i += kWave) plan[1 + sum + i] = cuts[b + i];
-    if (s + 1 == P.nseg && lane_id() == 0) {
-        plan[0] = sum + cnt;
-        plan[1 + sum + cnt] = P.T;
-    }
-}
-
-// Packing for larger draws: one workgroup scans the per-segment counts, then
-// every wavefront copies whole segment lists into the plan.
-__global__ __launch_bounds__(1024) void k_plan_pack(PlanArgs P, const uint32_t *cuts, uint32_t *ncuts,
-                                                    uint32_t *plan) {
-    __shared__ uint32_t tmp[16];
-    if (plan_is_aligned(P.fail, P.epoch)) return;
-    const uint32_t E = (P.nseg + 1023) / 1024;
-    const uint32_t lo = min(P.nseg, threadIdx.x * E), hi = min(P.nseg, lo + E);
-    uint32_t sum = 0;
-    for (uint32_t s = lo; s < hi; ++s) sum += ncuts[s];
-    uint32_t total;
-    uint32_t run = block_excl_scan<1024>(sum, tmp, total);
-    __syncthreads();   // every count is read before any is overwritten
-    for (uint32_t s = lo; s < hi; ++s) {
-        const uint32_t cnt = ncuts[s];
-        ncuts[s] = run;   // becomes the segment's offset in the plan
-        run += cnt;
-    }
-    __threadfence_block();
+    const uint32_t tid = threadIdx.x, s = blockIdx.x;
+    const uint32_t b = seg_lo(P, s), e = seg_hi(P, s), len = e - b;
+    const uint32_t fan = plan_fan_in(P.tmax), k0 = s / fan * fan;
+    uint32_t *s_nx = (uint32_t *)smem;                    // seg_len entries
+    uint32_t *s_cut = s_nx + P.seg_len;                   // seg_len entries
+    uint16_t *s_t = (uint16_t *)(s_cut + P.seg_len);      // the group's earlier tables
+    for (uint32_t i = tid; i < len; i += 256) s_nx[i] = P.next[b + i];
+    const uint32_t m = direct ? 0u : (s - k0) * P.tmax;
+    for (uint32_t i = tid; i < m; i += 256) s_t[i] = tab0[(size_t)k0 * P.tmax + i];
     __syncthreads();
-    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-    for (uint32_t s = w; s < P.nseg; s += 1024 / kWave) {
-        const uint32_t b = seg_lo(P, s);
-        // read past the CU's L1: other wavefronts rewrote these words above
-        const uint32_t off = __hip_atomic_load(&ncuts[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t cnt =
-            (s + 1 < P.nseg ? __hip_atomic_load(&ncuts[s + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : total) -
-            off;
-        for (uint32_t i = lane; i < cnt; i += kWave) plan[1 + off + i] = cuts[b + i];
+    if (tid == 0) {
+        uint32_t x = direct ? up[s] : up[s / fan];
+        for (uint32_t k = 0; k < m / max(P.tmax, 1u) && x != kEnd; ++k) x = s_t[k * P.tmax + x];
+        uint32_t n = 0;
+        if (x != kEnd)
+            for (uint32_t t = b + x; t < e; t = s_nx[t - b]) s_cut[n++] = t;
+        s_cnt = n;
+        if (s == 0) __hip_atomic_store(&status[0], ((unsigned long long)P.epoch << 32) | (2ull << 30) | n,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else __hip_atomic_store(&status[s], ((unsigned long long)P.epoch << 32) | (1ull << 30) | n,
+                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (threadIdx.x == 0) {
-        plan[0] = total;
-        plan[1 + total] = P.T;
+    __syncthreads();
+    const uint32_t cnt = s_cnt;
+    if (tid < kWave) {
+        const uint32_t off = s == 0 ? 0u : plan_lookback(status, s, cnt, P.epoch, P.err);
+        if (tid == 0) s_off = off;
+    }
+    __syncthreads();
+    const uint32_t off = s_off;
+    for (uint32_t i = tid; i < cnt; i += 256) plan[1 + off + i] = s_cut[i];
+    if (s + 1 == P.nseg && tid == 0) {
+        plan[0] = off + cnt;
+        plan[1 + off + cnt] = P.T;
     }
 }
 

@@ -55,6 +55,7 @@ struct vr_ctx {
     std::string error;
     CtxWords *d_words = nullptr;
     Scratch status, agg, plan, plan_work, tune, shaded;   // shaded: MULTI's vertex pass
+    Scratch plan_status;                                   // the planner's epoch-tagged look-back words
     Scratch selftest;                                      // vr_math_selftest's counter
     uint32_t host_err = 0;   // data error found on the host, reported by vr_sync
     uint32_t plan_epoch = 0;  // numbers planning calls (0 is never used)
@@ -397,7 +398,7 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     std::vector<uint32_t> counts{nseg};
     while (counts.back() > fan) counts.push_back((counts.back() + fan - 1) / fan);
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t bytes = al(4ull * T) * 2 + al(4ull * nseg);
+    size_t bytes = al(4ull * T);
     std::vector<size_t> tab_off, ent_off;
     for (uint32_t cnt : counts) {
         tab_off.push_back(bytes);
@@ -407,10 +408,12 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     }
     vr_status st = ensure(c, c->plan_work, bytes);
     if (st != VR_OK) return st;
+    // words tagged with a planning call's epoch: only ever written by the
+    // planner, zeroed when allocated, so no stale word carries a later epoch
+    st = ensure(c, c->plan_status, 8ull * nseg, /*zero=*/true);
+    if (st != VR_OK) return st;
     unsigned char *base = (unsigned char *)c->plan_work.ptr;
     uint32_t *next = (uint32_t *)base;
-    uint32_t *cuts = (uint32_t *)(base + al(4ull * T));
-    uint32_t *ncuts = (uint32_t *)(base + 2 * al(4ull * T));
     auto tab = [&](size_t l) { return (uint16_t *)(base + tab_off[l]); };
     auto ent = [&](size_t l) { return (uint16_t *)(base + ent_off[l]); };
     PlanArgs P{};
@@ -443,16 +446,15 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     const size_t top = counts.size() - 1;
     hipLaunchKernelGGL(k_plan_top, dim3(1), dim3(256), 2 * counts[top] * tmax, c->stream, tmax, counts[top],
                        (const uint16_t *)tab(top), ent(top), (const uint32_t *)P.fail, P.epoch);
-    for (size_t l = top; l-- > 0;)
+    for (size_t l = top; l-- > 1;)
         hipLaunchKernelGGL(k_plan_resolve, dim3(counts[l + 1]), dim3(256), grp_lds, c->stream, tmax, counts[l],
                            (const uint16_t *)tab(l), (const uint16_t *)ent(l + 1), ent(l), (const uint32_t *)P.fail,
                            P.epoch);
-    hipLaunchKernelGGL(k_plan_emit, dim3(nseg), dim3(64), 4 * L, c->stream, P, (const uint16_t *)ent(0), cuts, ncuts);
-    if (nseg <= kPackSegs)
-        hipLaunchKernelGGL(k_plan_pack_seg, dim3(nseg), dim3(64), 0, c->stream, P, (const uint32_t *)cuts,
-                           (const uint32_t *)ncuts, d_plan);
-    else
-        hipLaunchKernelGGL(k_plan_pack, dim3(1), dim3(1024), 0, c->stream, P, (const uint32_t *)cuts, ncuts, d_plan);
+    // level 0: entries, batch starts and packing in one launch
+    const uint32_t direct = top == 0 ? 1u : 0u;
+    hipLaunchKernelGGL(k_plan_emit, dim3(nseg), dim3(256), 8 * L + (direct ? 0u : grp_lds), c->stream, P,
+                       (const uint16_t *)tab(0), (const uint16_t *)ent(direct ? 0 : 1), direct,
+                       (unsigned long long *)c->plan_status.ptr, d_plan);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
 }
@@ -678,7 +680,7 @@ vr_status frame_variants(vr_ctx *c, const DrawDesc *desc, const FrameNeeds *need
             per_cu = frame_variant_dispatch(nullptr, v, nullptr, false);
             if (occ_cache) (*occ_cache)[ck] = per_cu;
         }
-        const uint64_t want = std::max<uint64_t>(1, (need.units + kFrameChunk - 1) / kFrameChunk);
+        const uint64_t want = std::max<uint64_t>(1, (need.units + frame_chunk(v.mode) - 1) / frame_chunk(v.mode));
         v.grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)std::max(1, c->num_cus * per_cu));
         vars.push_back(v);
         lo = hi;
@@ -723,7 +725,7 @@ void vr_destroy(vr_ctx *c) {
     if (!c) return;
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
-    for (Scratch *s : {&c->status, &c->agg, &c->plan, &c->plan_work, &c->tune, &c->shaded})
+    for (Scratch *s : {&c->status, &c->agg, &c->plan, &c->plan_work, &c->tune, &c->shaded, &c->plan_status})
         if (s->ptr) (void)hipFree(s->ptr);
     for (auto &pr : c->ev_pool) {
         (void)hipEventDestroy(pr.first);
@@ -1329,17 +1331,18 @@ vr_status vr_autotune(vr_ctx *c, const uint32_t *d_idx, uint64_t num_indices, co
             ok = vr_process_draw(c, d_idx, num_indices, d_vtx, V, sh, k.strategy, k.batch_tris, &o, &out) == VR_OK;
         c->timing = false;
         VR_HIP(c, hipStreamSynchronize(c->stream));
-        float sum = 0.0f;
+        // the fastest repetition: the least disturbed by other work on the device
+        float fastest = -1.0f;
         for (size_t j = first; j < c->ev_used; ++j) {
             float ms = 0.0f;
             VR_HIP(c, hipEventElapsedTime(&ms, c->ev_pool[j].first, c->ev_pool[j].second));
-            sum += ms;
+            if (fastest < 0.0f || ms < fastest) fastest = ms;
         }
         const size_t timed = c->ev_used - first;
         c->ev_used = first;
         if (!ok || timed == 0) continue;
         VR_HIP(c, hipMemcpy(&k.invocations, counters, sizeof(uint64_t), hipMemcpyDeviceToHost));
-        k.kernel_ms = sum / (float)timed;
+        k.kernel_ms = fastest;
         if (best_ms < 0.0f || k.kernel_ms < best_ms) {
             best_ms = k.kernel_ms;
             best_i = i;
