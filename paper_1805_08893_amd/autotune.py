@@ -98,7 +98,7 @@ class Autotuner:
     """Chooses a configuration per mesh class, timing the first draw of each
     class; `table` maps class -> {strategy, batch_tris, max_unique, ...}."""
 
-    def __init__(self, ctx, candidates=DEFAULT_CANDIDATES, path=None, sample_tris=262144, min_tris=131072):
+    def __init__(self, ctx, candidates=DEFAULT_CANDIDATES, path=None, sample_tris=1 << 20, min_tris=1 << 20):
         self.ctx = ctx
         self.candidates = candidates
         self.path = path

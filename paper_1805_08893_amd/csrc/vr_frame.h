@@ -22,10 +22,14 @@ namespace vr {
 
 enum FrameMode : uint32_t { kFrameSort = 0, kFrameHash = 1, kFramePHash = 2, kFrameBallot = 3, kFrameNaive = 4 };
 constexpr uint32_t kFrameNT = 256;
-// Consecutive units a workgroup takes at a time: 4, or 16 naive chunks of 256
-// corners (small units, whose draw lookup would otherwise weigh).
-__host__ __device__ constexpr uint32_t frame_chunk(uint32_t mode) { return mode == kFrameNaive ? 16u : 4u; }
+// Consecutive units a workgroup takes at a time.  A workgroup runs its
+// units one after another, each a chain of index load, vertex gather,
+// shading and stores, so larger chunks leave a longer tail: 16 naive units
+// per chunk made the scene's naive variants 2-3 times slower than 4, and a
+// deduplicated unit is several times longer than a naive one.
+__host__ __device__ constexpr uint32_t frame_chunk(uint32_t mode) { return mode == kFrameNaive ? 2u : 1u; }
 constexpr uint32_t kFrameMaxDraws = 4096;
+static_assert(VR_MAX_FRAME_DRAWS <= kFrameMaxDraws, "k_frame_prepare holds every draw of a frame");
 
 // One persistent launch of a frame: the draws of one variant (order
 // positions [lo, hi)), its kernel's LDS and its grid.
@@ -80,29 +84,35 @@ __device__ __forceinline__ void frame_draw_units(const DrawDesc &D, uint32_t &un
 }
 
 // One workgroup: unit and slot bases of the draws in variant order
-// (position k is draw order[k]), totals last.
+// (position k is draw order[k]), totals last.  Thread t owns positions
+// t*E .. t*E+E-1 (E <= kFrameMaxDraws / 1024); their counts are kept in
+// registers between the scan and the writes.
 __global__ __launch_bounds__(1024) void k_frame_prepare(const DrawDesc *draws, const uint32_t *order, uint32_t n,
                                                         uint32_t *unit_base, uint32_t *slot_base, uint32_t *err) {
+    constexpr uint32_t kE = kFrameMaxDraws / 1024;
     __shared__ uint32_t tmp[16];
     const uint32_t E = (n + 1023) / 1024;
     const uint32_t lo = min(n, threadIdx.x * E), hi = min(n, lo + E);
+    uint32_t cu[kE], cs[kE];
     uint32_t su = 0, ss = 0;
-    for (uint32_t k = lo; k < hi; ++k) {
-        uint32_t u, s;
-        frame_draw_units(draws[order[k]], u, s, err);
-        su += u;
-        ss += s;
+#pragma unroll
+    for (uint32_t j = 0; j < kE; ++j) {
+        cu[j] = cs[j] = 0;
+        if (lo + j < hi) frame_draw_units(draws[order[lo + j]], cu[j], cs[j], err);
+        su += cu[j];
+        ss += cs[j];
     }
     uint32_t tu, ts;
     uint32_t ru = block_excl_scan<1024>(su, tmp, tu);
     uint32_t rs = block_excl_scan<1024>(ss, tmp, ts);
-    for (uint32_t k = lo; k < hi; ++k) {
-        uint32_t u, s;
-        frame_draw_units(draws[order[k]], u, s, err);
-        unit_base[k] = ru;
-        slot_base[k] = rs;
-        ru += u;
-        rs += s;
+#pragma unroll
+    for (uint32_t j = 0; j < kE; ++j) {
+        if (lo + j < hi) {
+            unit_base[lo + j] = ru;
+            slot_base[lo + j] = rs;
+        }
+        ru += cu[j];
+        rs += cs[j];
     }
     if (threadIdx.x == 0) {
         unit_base[n] = tu;
@@ -199,14 +209,21 @@ __global__ __launch_bounds__(kFrameNT) void k_frame(const DrawDesc *draws, const
     }
 }
 
-// Per draw (order position k): counters = the sum of its aggregates;
-// dtot[k] = its invocations.
-__global__ __launch_bounds__(64) void k_frame_finish(const DrawDesc *draws, const uint32_t *order,
-                                                     const uint32_t *slot_base, const unsigned long long *agg,
-                                                     unsigned long long *dtot) {
-    const uint32_t d = blockIdx.x;
+// Per draw (order position d): counters = the sum of its aggregates;
+// dtot[d] = its invocations.  One wavefront per draw, 16 per workgroup.
+__global__ __launch_bounds__(1024) void k_frame_finish(const DrawDesc *draws, const uint32_t *order, uint32_t n,
+                                                       const uint32_t *slot_base, const unsigned long long *agg,
+                                                       unsigned long long *dtot) {
+    const uint32_t d = blockIdx.x * 16 + threadIdx.x / kWave;
+    if (d >= n) return;
     unsigned long long sum = 0;
-    for (uint32_t i = slot_base[d] + lane_id(); i < slot_base[d + 1]; i += kWave) sum += agg[i];
+    const uint32_t i1 = slot_base[d + 1];
+    for (uint32_t i = slot_base[d] + lane_id(); i < i1; i += 4 * kWave) {   // four loads in flight
+        unsigned long long v[4];
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) v[j] = i + j * kWave < i1 ? agg[i + j * kWave] : 0ull;
+        sum += v[0] + v[1] + v[2] + v[3];
+    }
 #pragma unroll
     for (int s = 32; s > 0; s >>= 1) sum += __shfl_xor(sum, s, kWave);
     if (lane_id() == 0) {

@@ -535,8 +535,8 @@ void enqueue_frame_kernels(const FrameLaunch &L, hipStream_t s) {
     hipLaunchKernelGGL(k_frame_prepare, dim3(1), dim3(1024), 0, s, L.draws, L.order, L.n, L.unit_base, L.slot_base,
                        L.err);
     for (uint32_t i = 0; i < L.num_variants; ++i) frame_variant_dispatch(&L, L.variants[i], s, true);
-    hipLaunchKernelGGL(k_frame_finish, dim3(L.n), dim3(64), 0, s, L.draws, L.order, (const uint32_t *)L.slot_base,
-                       (const unsigned long long *)L.agg, L.dtot);
+    hipLaunchKernelGGL(k_frame_finish, dim3((L.n + 15) / 16), dim3(1024), 0, s, L.draws, L.order, L.n,
+                       (const uint32_t *)L.slot_base, (const unsigned long long *)L.agg, L.dtot);
     if (L.total_inv)
         hipLaunchKernelGGL(k_frame_total, dim3(1), dim3(1024), 0, s, (const unsigned long long *)L.dtot, L.n,
                            L.total_inv);
