@@ -60,7 +60,7 @@ __host__ __device__ inline uint32_t plan_fan_in(uint32_t tmax) {
 // power-of-two hash table at most 8/9 full.
 template <uint32_t TMC>
 struct NextClass {
-    static constexpr uint32_t threads = TMC == 1024 ? 256 : 512;
+    static constexpr uint32_t threads = TMC == 512 ? 1024 : (TMC == 1024 ? 256 : 512);
     static constexpr uint32_t starts = threads;
     static constexpr uint32_t tris = starts + TMC;
     static constexpr uint32_t corners = 3 * tris;
