@@ -167,10 +167,17 @@ __device__ __forceinline__ void frame_unit(const DrawArgs &A, const vr_shader_pa
 // The persistent kernel of one variant: the draws at order positions
 // [lo, hi), whose units are unit_base[lo] .. unit_base[hi] - 1.  Dynamic LDS:
 // the variant's largest unit layout, then its draw bases (hi - lo + 1 words).
+// The hashing variants are held to eight wavefronts per SIMD, as in a single
+// draw.  The read-only inputs are restrict: k_frame_prepare writes them
+// before the launch and nothing writes them during it, which lets the
+// compiler read the descriptors and shader parameters with scalar loads.
 template <int MODE, int KIND>
-__global__ __launch_bounds__(kFrameNT) void k_frame(const DrawDesc *draws, const uint32_t *order, uint32_t lo,
-                                                    uint32_t hi, const vr_shader_params *shaders,
-                                                    const uint32_t *unit_base, const uint32_t *slot_base,
+__global__ __launch_bounds__(kFrameNT)
+__attribute__((amdgpu_waves_per_eu(MODE == kFrameHash || MODE == kFramePHash ? 8 : 1))) void k_frame(const DrawDesc *__restrict__ draws,
+                                                    const uint32_t *__restrict__ order, uint32_t lo, uint32_t hi,
+                                                    const vr_shader_params *__restrict__ shaders,
+                                                    const uint32_t *__restrict__ unit_base,
+                                                    const uint32_t *__restrict__ slot_base,
                                                     unsigned long long *agg, uint32_t unit_lds,
                                                     uint32_t ballot_stride, uint32_t *err,
                                                     unsigned long long *total_inv) {
@@ -186,17 +193,23 @@ __global__ __launch_bounds__(kFrameNT) void k_frame(const DrawDesc *draws, const
     DrawArgs A{};
     const vr_shader_params *sh = shaders;
     uint32_t nb = 0;
-    for (uint32_t c0 = s_base[0] + blockIdx.x * kChunk; c0 < U; c0 += G * kChunk) {
+    // The draw index and everything loaded through it are the same in every
+    // lane; reading the LDS bases through readfirstlane lets the compiler see
+    // that, so the descriptor and the shader parameters stay in scalar
+    // registers (as kernel arguments do in a single draw) instead of taking
+    // vector registers and vector loads.
+    auto base_at = [&](uint32_t k) { return (uint32_t)__builtin_amdgcn_readfirstlane(s_base[k]); };
+    for (uint32_t c0 = base_at(0) + blockIdx.x * kChunk; c0 < U; c0 += G * kChunk) {
         // the draw of unit c0: largest k with s_base[k] <= c0
         uint32_t a = 0, b = m;   // invariant: s_base[a] <= c0 < s_base[b]
         while (b - a > 1) {
             const uint32_t mid = (a + b) / 2;
-            if (s_base[mid] <= c0) a = mid;
+            if (base_at(mid) <= c0) a = mid;
             else b = mid;
         }
         uint32_t k = a;
         for (uint32_t u = c0; u < min(U, c0 + kChunk); ++u) {
-            while (u >= s_base[k + 1]) ++k;   // units of empty draws are skipped
+            while (u >= base_at(k + 1)) ++k;   // units of empty draws are skipped
             if (k != kd) {   // descriptors are loaded once per draw, not per unit
                 kd = k;
                 const DrawDesc D = draws[order[lo + k]];
@@ -204,7 +217,7 @@ __global__ __launch_bounds__(kFrameNT) void k_frame(const DrawDesc *draws, const
                 sh = shaders + D.shader;
                 nb = slot_base[lo + k + 1] - slot_base[lo + k];
             }
-            frame_unit<MODE, KIND>(A, *sh, u - s_base[k], nb, smem, ballot_stride);
+            frame_unit<MODE, KIND>(A, *sh, u - base_at(k), nb, smem, ballot_stride);
         }
     }
 }
