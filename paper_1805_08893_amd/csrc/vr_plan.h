@@ -78,7 +78,10 @@ struct NextClass {
     static_assert(lds <= 160 * 1024, "window fits the LDS");
 };
 
-// k_plan_check for caps up to TMC triangles: one window per workgroup.
+// k_plan_check for caps up to TMC triangles: one window per workgroup.  The
+// table is sized for the class whatever N_pmax: a sparser table keeps the
+// longest probe chain of a lockstep round short on windows of distinct
+// indices.
 template <uint32_t TMC>
 struct CheckClass {
     static constexpr uint32_t threads = TMC <= 1024 ? 256 : 1024;
@@ -119,7 +122,7 @@ template <uint32_t TMC>
 __global__ __launch_bounds__(CheckClass<TMC>::threads) void k_plan_check(PlanArgs P, uint32_t *plan) {
     using C = CheckClass<TMC>;
     constexpr uint32_t NT = C::threads, kPer = C::per, kBits = C::bits;
-    __shared__ uint32_t s_tab[1u << kBits];
+    __shared__ __attribute__((aligned(16))) uint32_t s_tab[1u << kBits];
     __shared__ uint32_t s_tmp[NT / kWave];
     const uint32_t tid = threadIdx.x;
     const uint32_t t0 = blockIdx.x * P.tmax, t1 = min(P.T, t0 + P.tmax);
@@ -148,7 +151,8 @@ __global__ __launch_bounds__(CheckClass<TMC>::threads) void k_plan_check(PlanArg
             key[k] = 0;
         }
     }
-    for (uint32_t q = tid; q < (1u << kBits); q += NT) s_tab[q] = kEmpty;
+    constexpr uint32_t mask = (1u << kBits) - 1;
+    for (uint32_t q = 4 * tid; q <= mask; q += 4 * NT) *(uint4 *)&s_tab[q] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
     __syncthreads();
     uint32_t slot[kPer], pending = 0, fresh = 0;
 #pragma unroll
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(CheckClass<TMC>::threads) void k_plan_check(PlanArg
                     fresh += prev == kEmpty;
                     pending &= ~(1u << k);
                 } else {
-                    slot[k] = (slot[k] + 1) & ((1u << kBits) - 1);
+                    slot[k] = (slot[k] + 1) & mask;
                 }
             }
         }
@@ -185,7 +189,7 @@ __global__ __launch_bounds__(NextClass<TMC>::threads) void k_plan_next(PlanArgs 
     if (plan_is_aligned(P.fail, P.epoch)) return;
     // LDS regions are reused once their first contents are dead:
     //   s_a: indices (insert) -> corner positions grouped by slot + start counts
-    //   s_tab: keys (insert) -> bucket starts | bucket ends (2 x uint16)
+    //   s_tab: keys (insert) -> bucket start | bucket end << 16 per slot
     //   s_cnt: slot counts -> 3 x 16-bit previous occurrence per triangle
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     uint32_t *s_a = (uint32_t *)smem;
@@ -197,7 +201,9 @@ __global__ __launch_bounds__(NextClass<TMC>::threads) void k_plan_next(PlanArgs 
     uint32_t *s_key = s_a;
     uint16_t *s_arr = (uint16_t *)s_a;                       // 3 * kNextTris entries
     int *s_diff = (int *)(s_a + (3 * kNextTris + 1) / 2);    // kNextBlock + 1 entries
-    uint16_t *s_start = (uint16_t *)s_tab, *s_end = s_start + kNextSlots;
+    uint32_t *s_se = s_tab;
+    constexpr uint32_t E = kNextSlots / NT;   // slots per thread in the clears and the scan
+    static_assert(E % 8 == 0, "slots are handled in 16-byte LDS accesses");
     const uint32_t tid = threadIdx.x;
     const uint32_t c0 = blockIdx.x * kNextBlock;
     const uint32_t r1 = min(P.T, c0 + kNextBlock + P.tmax);
@@ -223,10 +229,11 @@ __global__ __launch_bounds__(NextClass<TMC>::threads) void k_plan_next(PlanArgs 
             }
         }
     }
-    for (uint32_t s = tid; s < kNextSlots; s += NT) {
-        s_tab[s] = kEmpty;
-        s_cnt[s] = 0;
-    }
+#pragma unroll
+    for (uint32_t j = 0; j < E / 4; ++j)
+        ((uint4 *)(s_tab + tid * E))[j] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+#pragma unroll
+    for (uint32_t j = 0; j < E / 8; ++j) ((uint4 *)(s_cnt + tid * E))[j] = make_uint4(0, 0, 0, 0);
     __syncthreads();
     // insertion: every thread owns corners tid + NT*k (k < kPer) and probes
     // them in lockstep rounds so their LDS round trips overlap
@@ -260,17 +267,34 @@ __global__ __launch_bounds__(NextClass<TMC>::threads) void k_plan_next(PlanArgs 
         }
     }
     __syncthreads();
-    {   // bucket starts: exclusive scan of the counts, 16 slots per thread
-        constexpr uint32_t E = kNextSlots / NT;
+    {   // bucket starts: exclusive scan of the counts, E slots per thread;
+        // each slot's word becomes start | end << 16 with the end (the fill
+        // cursor) starting at the start
+        const uint4 *c4 = (const uint4 *)(s_cnt + tid * E);
+        auto half_sum = [](uint32_t w) { return (w & 0xFFFFu) + (w >> 16); };
         uint32_t sum = 0;
-        for (uint32_t j = 0; j < E; ++j) sum += s_cnt[tid * E + j];
+#pragma unroll
+        for (uint32_t j = 0; j < E / 8; ++j) {
+            const uint4 w = c4[j];
+            sum += half_sum(w.x) + half_sum(w.y) + half_sum(w.z) + half_sum(w.w);
+        }
         uint32_t total;
         uint32_t run = block_excl_scan<NT>(sum, s_tmp, total);
-        for (uint32_t j = 0; j < E; ++j) {
-            const uint32_t cnt = s_cnt[tid * E + j];
-            s_start[tid * E + j] = (uint16_t)run;
-            s_end[tid * E + j] = (uint16_t)run;   // becomes the bucket end (cursor)
-            run += cnt;
+        uint4 *o4 = (uint4 *)(s_se + tid * E);
+#pragma unroll
+        for (uint32_t j = 0; j < E / 8; ++j) {
+            const uint4 w = c4[j];
+            const uint32_t cw[4] = {w.x, w.y, w.z, w.w};
+            uint32_t o[8];
+#pragma unroll
+            for (uint32_t h = 0; h < 4; ++h) {
+                o[2 * h] = run * 0x10001u;
+                run += cw[h] & 0xFFFFu;
+                o[2 * h + 1] = run * 0x10001u;
+                run += cw[h] >> 16;
+            }
+            o4[2 * j] = make_uint4(o[0], o[1], o[2], o[3]);
+            o4[2 * j + 1] = make_uint4(o[4], o[5], o[6], o[7]);
         }
     }
     __syncthreads();
@@ -279,8 +303,8 @@ __global__ __launch_bounds__(NextClass<TMC>::threads) void k_plan_next(PlanArgs 
         const uint32_t i = tid + NT * k;
         if (i < n) {
             const uint32_t sl = slot[k];
-            const uint32_t old = atomicAdd((uint32_t *)&s_end[sl & ~1u], (sl & 1u) ? 0x10000u : 1u);
-            s_arr[(sl & 1u) ? (old >> 16) : (old & 0xFFFFu)] = (uint16_t)i;
+            const uint32_t old = atomicAdd(&s_se[sl], 0x10000u);
+            s_arr[old >> 16] = (uint16_t)i;
         }
     }
     for (uint32_t c = tid; c <= kNextBlock; c += NT) s_diff[c] = 0;
@@ -296,8 +320,9 @@ __global__ __launch_bounds__(NextClass<TMC>::threads) void k_plan_next(PlanArgs 
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
         const uint32_t i = tid + NT * k;
-        q[k] = i < n ? s_start[slot[k]] : 0u;
-        qe[k] = i < n ? s_end[slot[k]] : 0u;
+        const uint32_t se = i < n ? s_se[slot[k]] : 0u;
+        q[k] = se & 0xFFFFu;
+        qe[k] = se >> 16;
         best[k] = kNone;
     }
     for (bool more = true; more;) {
