@@ -692,8 +692,7 @@ def serving_benchmark(stage, seed=11, n=2000, rate=500.0, budget=64 << 30, small
                 srv.submit(r)
             srv.drain(n)
             t0 = time.perf_counter()
-            for r in reqs:                      # burst: everything at once
-                srv.submit(r)
+            srv.submit_many(reqs)               # burst: everything at once, in one call
             got = srv.drain(n)
             burst = serve.summarize(got, time.perf_counter() - t0)
             got, late, wall = serve.replay(srv, reqs, tr["arrival"])

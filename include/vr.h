@@ -480,6 +480,15 @@ vr_status vr_server_add_mesh(vr_server *server, const uint32_t *d_indices, uint6
  * mesh, or any argument vr_process_draw would reject; VR_ERR_CAPACITY when
  * its output can never fit in the budget; VR_ERR_BUSY after destroy began. */
 vr_status vr_server_submit(vr_server *server, const vr_request *request, uint64_t *ticket);
+/* Queues requests[0..n) in order under one acquisition of the server's lock,
+ * so the scheduler sees them together (a burst is not split into ticks by
+ * the caller's submission rate).  Each request is checked as by
+ * vr_server_submit; at the first rejected one the call stops and returns its
+ * status.  *accepted = the number queued (their tickets in tickets[0..*accepted));
+ * the rejected request and the ones after it are not queued.  VR_ERR_ARG for
+ * NULL pointers. */
+vr_status vr_server_submit_many(vr_server *server, const vr_request *requests, uint32_t n, uint64_t *tickets,
+                                uint32_t *accepted);
 /* Returns up to `cap` finished requests, oldest first, waiting up to
  * timeout_ms for the first one (0 = do not wait). */
 vr_status vr_server_poll(vr_server *server, vr_completion *out, uint32_t cap, uint32_t *count, uint32_t timeout_ms);

@@ -340,32 +340,43 @@ __host__ __device__ inline uint32_t sort_groups(uint32_t max_idx, uint32_t nt) {
     return (g + 3u) & ~3u;
 }
 
-// The local ids and the unique list live through the whole unit; the
-// shaded vertices (written after deduplication) share their region with
-// what deduplication alone uses: the indices, then the sort's two position
-// buffers and its per-digit counts (uint8) and offsets (uint16), or the
-// hash table and the first-position words.  sv_rows shaded vertices are
+// The local ids and the unique list live from deduplication to the end of
+// the unit; the shaded vertices (written after deduplication) share their
+// region with what deduplication alone uses: the indices, then the sort's
+// two position buffers and its per-digit counts (uint8) and offsets
+// (uint16), or the hash table and the first-position words.  sv_rows shaded vertices are
 // kept: every unique vertex of a unit when corners are assembled, else one
 // stage of nt rows through which the shaded vertices stream out.
 __host__ __device__ inline DedupLds dedup_lds_layout(int mode, uint32_t max_idx, uint32_t max_uniq,
                                                      uint32_t hash_bits, uint32_t nt, uint32_t sv_rows) {
     DedupLds L{};
     uint32_t off = 0;
-    L.local = off; off += align16(2 * max_idx);   // uint16: hash slots < 8192, then ids < max_idx
-    L.uniq = off;  off += align16(4 * max_uniq);
-    L.sv = off;
-    uint32_t d = off;
-    L.keys = d;    d += align16(4 * max_idx);
     if (mode == kSort) {
+        // The sort writes the local ids and the unique list only after its
+        // last pass, so they sit in the space of its count tables, past the
+        // buffers the run-end scan still reads and past the shaded vertices
+        // (written from the start once the sort's buffers are dead).
+        uint32_t d = 0;
+        L.keys = d;  d += align16(4 * max_idx);
         L.pairs = d; d += align16(4 * max_idx);   // two uint16 position buffers
         L.stab = d;  d += 3u * 256u * sort_groups(max_idx, nt);
+        L.sv = 0;
+        uint32_t lu = max(align16(48 * sv_rows), L.stab);
+        L.local = lu; lu += align16(2 * max_idx);   // uint16 ids < max_idx
+        L.uniq = lu;  lu += align16(4 * max_uniq);
         L.table = L.first = 0;
+        off = max(lu, d);
     } else {
+        L.local = off; off += align16(2 * max_idx);   // uint16: hash slots < 8192, then ids < max_idx
+        L.uniq = off;  off += align16(4 * max_uniq);
+        L.sv = off;
+        uint32_t d = off;
+        L.keys = d;    d += align16(4 * max_idx);
         L.pairs = L.stab = 0;
         L.table = d; d += align16(4u << hash_bits);
         L.first = d; d += align16(4u << hash_bits);
+        off = max(align16(off + 48 * sv_rows), align16(d));
     }
-    off = max(align16(off + 48 * sv_rows), align16(d));
     L.tmp = off;  off += 64;
     L.total = off;
     return L;
@@ -730,7 +741,7 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
 // latency.  The sort stays at its natural allocation: its LDS caps it at
 // six workgroups per CU, and the bound would only add spills.
 template <int NT, int MODE, int KIND>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MODE == kSort ? 1 : 8))) void k_dedup(DrawArgs A, vr_shader_params sh, uint32_t base, uint32_t stride) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MODE == kSort ? 7 : 8))) void k_dedup(DrawArgs A, vr_shader_params sh, uint32_t base, uint32_t stride) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     if (base == 0) clear_counters(A);
     const uint32_t nb = launch_units(A, batch_count(A));

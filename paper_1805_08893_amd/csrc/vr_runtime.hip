@@ -1799,9 +1799,9 @@ vr_status vr_server_add_mesh(vr_server *s, const uint32_t *d_idx, uint64_t num_i
     return VR_OK;
 }
 
-vr_status vr_server_submit(vr_server *s, const vr_request *r, uint64_t *ticket) {
-    if (!s || !r || !ticket) return VR_ERR_ARG;
-    std::lock_guard<std::mutex> lk(s->m);
+// Validates and queues one request; the caller holds s->m and wakes the
+// scheduler.
+static vr_status server_submit_locked(vr_server *s, const vr_request *r, uint64_t *ticket) {
     if (s->stop) return server_fail(s, VR_ERR_BUSY, "the server is shutting down");
     if (r->mesh >= s->meshes.size()) return server_fail(s, VR_ERR_ARG, "unknown mesh %u", r->mesh);
     const ServerMesh &M = s->meshes[r->mesh];
@@ -1846,8 +1846,29 @@ vr_status vr_server_submit(vr_server *s, const vr_request *r, uint64_t *ticket) 
                            (unsigned long long)bytes);
     s->reqs[t] = R;
     *ticket = t;
-    s->cv_work.notify_one();
     return VR_OK;
+}
+
+vr_status vr_server_submit(vr_server *s, const vr_request *r, uint64_t *ticket) {
+    if (!s || !r || !ticket) return VR_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->m);
+    const vr_status st = server_submit_locked(s, r, ticket);
+    if (st == VR_OK) s->cv_work.notify_one();
+    return st;
+}
+
+vr_status vr_server_submit_many(vr_server *s, const vr_request *r, uint32_t n, uint64_t *tickets,
+                                uint32_t *accepted) {
+    if (!s || !accepted || (n && (!r || !tickets))) return VR_ERR_ARG;
+    *accepted = 0;
+    std::lock_guard<std::mutex> lk(s->m);
+    vr_status st = VR_OK;
+    for (uint32_t i = 0; i < n && st == VR_OK; ++i) {
+        st = server_submit_locked(s, r + i, tickets + i);
+        if (st == VR_OK) ++*accepted;
+    }
+    if (*accepted) s->cv_work.notify_one();
+    return st;
 }
 
 vr_status vr_server_poll(vr_server *s, vr_completion *out, uint32_t cap, uint32_t *count, uint32_t timeout_ms) {

@@ -48,6 +48,12 @@ class Server:
         self.check(st)
         return t
 
+    def submit_many(self, requests):
+        """Queues all requests under one lock (the scheduler sees them together)."""
+        st, tickets = vr.vr_server_submit_many(self.h, requests)
+        self.check(st)
+        return tickets
+
     def poll(self, cap=256, timeout_ms=0):
         st, out = vr.vr_server_poll(self.h, cap, timeout_ms)
         self.check(st)

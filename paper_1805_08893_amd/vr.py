@@ -35,7 +35,7 @@ EXPORTS = ["vr_create", "vr_destroy", "vr_set_stream", "vr_check_args", "vr_plan
            "vr_sync", "vr_walk_step", "vr_stream_create", "vr_stream_push", "vr_stream_finish",
            "vr_stream_destroy", "vr_frame_create", "vr_frame_run", "vr_frame_destroy", "vr_process_draws", "vr_autotune",
            "vr_set_kernel_timing", "vr_kernel_times", "vr_math_selftest", "vr_last_error", "vr_server_create", "vr_server_add_mesh",
-           "vr_server_submit", "vr_server_poll", "vr_server_release", "vr_server_fetch", "vr_server_cancel", "vr_server_stats_get",
+           "vr_server_submit", "vr_server_submit_many", "vr_server_poll", "vr_server_release", "vr_server_fetch", "vr_server_cancel", "vr_server_stats_get",
            "vr_server_destroy", "vr_server_last_error", "vr_server_simulate"]
 
 
@@ -172,6 +172,8 @@ def lib():
         L.vr_server_create.argtypes = [C.c_int, C.POINTER(vr_server_config), C.POINTER(C.c_void_p)]
         L.vr_server_add_mesh.argtypes = [P, P, C.c_uint64, P, C.c_uint32, C.POINTER(C.c_uint32)]
         L.vr_server_submit.argtypes = [P, C.POINTER(vr_request), C.POINTER(C.c_uint64)]
+        L.vr_server_submit_many.argtypes = [P, C.POINTER(vr_request), C.c_uint32, C.POINTER(C.c_uint64),
+                                            C.POINTER(C.c_uint32)]
         L.vr_server_poll.argtypes = [P, C.POINTER(vr_completion), C.c_uint32, C.POINTER(C.c_uint32), C.c_uint32]
         L.vr_server_release.argtypes = [P, C.c_uint64]
         L.vr_server_cancel.argtypes = [P, C.c_uint64]
@@ -180,7 +182,7 @@ def lib():
         L.vr_server_simulate.argtypes = [C.POINTER(vr_server_config), C.POINTER(vr_sim_request), C.c_uint32,
                                          C.c_double, C.c_double, C.POINTER(vr_sim_result),
                                          C.POINTER(vr_server_stats)]
-        for f in ("vr_server_create", "vr_server_add_mesh", "vr_server_submit", "vr_server_poll",
+        for f in ("vr_server_create", "vr_server_add_mesh", "vr_server_submit", "vr_server_submit_many", "vr_server_poll",
                   "vr_server_release", "vr_server_fetch", "vr_server_cancel", "vr_server_stats_get", "vr_server_simulate"):
             getattr(L, f).restype = C.c_int
         L.vr_server_destroy.argtypes = [P]
@@ -483,6 +485,16 @@ def vr_server_submit(server, request):
     t = C.c_uint64()
     st = lib().vr_server_submit(server, C.byref(request), C.byref(t))
     return st, t.value
+
+
+def vr_server_submit_many(server, requests):
+    """(status, tickets of the requests queued: all of them when status is VR_OK)."""
+    n = len(requests)
+    arr = (vr_request * n)(*requests)
+    tickets = (C.c_uint64 * max(n, 1))()
+    acc = C.c_uint32()
+    st = lib().vr_server_submit_many(server, arr, n, tickets, C.byref(acc))
+    return st, [int(tickets[i]) for i in range(acc.value)]
 
 
 def vr_server_poll(server, cap=256, timeout_ms=0):

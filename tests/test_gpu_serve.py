@@ -1,6 +1,7 @@
 """Request server on the GPU: every request's result, alone or in any mix,
-equals the single-draw path's (bitwise corners, equal counts); admission
-under a tiny budget; argument errors and cancellation."""
+equals the single-draw path's (bitwise corners, equal counts); requests
+queued in one call; admission under a tiny budget; argument errors and
+cancellation."""
 import numpy as np
 import pytest
 
@@ -133,6 +134,41 @@ def test_mix_matches_the_oracle_directly():
             mine = srv.fetch(c["ticket"], size)
             assert np.array_equal(mine.view(np.uint32), o["corners"].view(np.uint32))
             srv.release(c["ticket"])
+
+
+def test_submit_many_matches_the_oracle_and_stops_at_a_rejected_request():
+    """Requests queued in one call are processed as if submitted one by one
+    (bitwise against the oracle); a rejected request in the middle ends the
+    call with its status, the ones before it queued and the ones after not;
+    an empty call queues nothing."""
+    from paper_1805_08893_amd import vr
+    from paper_1805_08893_amd.serve import Server
+    reqs = [r for r in _requests(14, 9) if r[2] <= 1500][:6]
+    with Server(64 << 20) as srv:
+        dev, ids = _register(srv, [(b, st) for b, st, *_ in reqs])
+        made = [vr.make_request(ids[(b, start)], size, sp, s, bt, nu, user=i)
+                for i, (b, start, size, sp, (s, bt, nu)) in enumerate(reqs)]
+        b0, start0 = reqs[0][0], reqs[0][1]
+        bad = vr.make_request(ids[(b0, start0)], _bases()[b0].num_tris - start0 + 1, reqs[0][3], vr.VR_NAIVE, 1,
+                              user=99)
+        st, tickets = vr.vr_server_submit_many(srv.h, made[:4] + [bad] + made[4:])
+        assert st == vr.VR_ERR_ARG and len(tickets) == 4
+        assert srv.submit_many([]) == []
+        assert len(srv.submit_many(made[4:])) == len(made) - 4
+        got = srv.drain(len(made), release=False)
+        assert sorted(c["user"] for c in got) == list(range(len(made)))
+        for c in got:
+            b, start, size, sp, (s, bt, nu) = reqs[c["user"]]
+            m = _bases()[b]
+            rc, o = vro.process_draw(m.indices[3 * start:3 * (start + size)], m.vertices, sp, s, bt,
+                                     vro.make_opts(max_unique=nu), corners=True)
+            assert rc == 0
+            assert c["status"] == vr.VR_OK
+            assert c["invocations"] == int(o["counters"][0]) and c["units"] == int(o["counters"][1])
+            mine = srv.fetch(c["ticket"], size)
+            assert np.array_equal(mine.view(np.uint32), o["corners"].view(np.uint32))
+            srv.release(c["ticket"])
+        assert srv.stats()["submitted"] == len(made)
 
 
 def test_tiny_budget_queues_and_stays_correct(stage):
