@@ -87,12 +87,14 @@ def committed_traffic(kernel):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def scene_benchmark(stage, seed=3, num_draws=2000, replays=10):
+def scene_benchmark(stage, seed=3, num_draws=2000, replays=10, table=None):
     """Many draws in one persistent launch (a hipGraph frame) against one
     launch per draw, with autotuned per-class configurations.  Draw sizes are
     log-normal in [100, 200000] triangles (mean about 5,000), each draw the
     first T_d triangles of a grid or icosphere base mesh in Hilbert or scan
-    order, shaders MVP, Phong-4 or Phong-16."""
+    order, shaders MVP, Phong-4 or Phong-16.  With `table` (a JSON path) the
+    autotuner's choices are read from it when it exists and written to it
+    otherwise, so that separate runs (profiler passes) use the same ones."""
     import torch
     from paper_1805_08893_amd import vr
     from paper_1805_08893_amd import workloads as W
@@ -108,7 +110,7 @@ def scene_benchmark(stage, seed=3, num_draws=2000, replays=10):
     Ts = np.clip(np.exp(rng.normal(np.log(5000.0) - 0.72, 1.2, num_draws)), 100, 200000).astype(np.int64)
     which = rng.integers(0, len(bases), num_draws)
     shade = rng.integers(0, len(shaders), num_draws)
-    tuner = Autotuner(stage.ctx)
+    tuner = Autotuner(stage.ctx, path=table)
     total_T = int(Ts.sum())
     corners = torch.empty((3 * total_T, 12), dtype=torch.float32, device="cuda")
     counters = torch.zeros((num_draws, 4), dtype=torch.int64, device="cuda")
@@ -131,6 +133,8 @@ def scene_benchmark(stage, seed=3, num_draws=2000, replays=10):
         off += T
     stage.check(stage.sync()[0])
     t_tune = time.perf_counter() - t_tune
+    if table:
+        tuner.save()
     # one launch per draw
     sh = [vr.make_shader(x) for x in shaders]
     outs = [vr.vr_outputs(c.data_ptr(), None, None, 0, None, None, None, 0, cnt.data_ptr())
@@ -759,6 +763,8 @@ def main():
     ap.add_argument("--only", default=None, help="run only this strategy in each step (profiling)")
     ap.add_argument("--no-scene", action="store_true", help="skip the many-draw frame measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--autotune-table", default=None, metavar="JSON",
+                    help="scene: read the autotuner's choices from this file if it exists, else write them")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the cold-cache runs, the small-grid latency and the heavy-shader orders")
     ap.add_argument("--sweep", action="store_true",
@@ -967,7 +973,7 @@ def main():
     scene = None
     if not args.no_scene and not args.only:
         try:
-            scene = scene_benchmark(stage)
+            scene = scene_benchmark(stage, table=args.autotune_table)
             progress("scene done")
         except Exception as exc:   # the headline line must still be printed
             scene = {"error": repr(exc)}
