@@ -35,6 +35,7 @@ static_assert(VR_MAX_FRAME_DRAWS <= kFrameMaxDraws, "k_frame_prepare holds every
 // positions [lo, hi)), its kernel's LDS and its grid.
 struct FrameVariant {
     uint32_t mode, kind, lo, hi, grid, unit_lds, ballot_stride, lds_total;
+    uint32_t occ;   // hashing variant held to eight wavefronts per SIMD (its LDS allows them)
 };
 
 struct DrawDesc {
@@ -167,13 +168,13 @@ __device__ __forceinline__ void frame_unit(const DrawArgs &A, const vr_shader_pa
 // The persistent kernel of one variant: the draws at order positions
 // [lo, hi), whose units are unit_base[lo] .. unit_base[hi] - 1.  Dynamic LDS:
 // the variant's largest unit layout, then its draw bases (hi - lo + 1 words).
-// The hashing variants are held to eight wavefronts per SIMD, as in a single
-// draw.  The read-only inputs are restrict: k_frame_prepare writes them
-// before the launch and nothing writes them during it, which lets the
-// compiler read the descriptors and shader parameters with scalar loads.
-template <int MODE, int KIND>
-__global__ __launch_bounds__(kFrameNT)
-__attribute__((amdgpu_waves_per_eu(MODE == kFrameHash || MODE == kFramePHash ? 8 : 1))) void k_frame(const DrawDesc *__restrict__ draws,
+// With OCC (hashing variants whose LDS lets eight workgroups reside) the
+// kernel is held to eight wavefronts per SIMD, as in a single draw.  The
+// read-only inputs are restrict: k_frame_prepare writes them before the
+// launch and nothing writes them during it, which lets the compiler read the
+// descriptors and shader parameters with scalar loads.
+template <int MODE, int KIND, bool OCC>
+__global__ __launch_bounds__(kFrameNT) __attribute__((amdgpu_waves_per_eu(OCC ? 8 : 1))) void k_frame(const DrawDesc *__restrict__ draws,
                                                     const uint32_t *__restrict__ order, uint32_t lo, uint32_t hi,
                                                     const vr_shader_params *__restrict__ shaders,
                                                     const uint32_t *__restrict__ unit_base,

@@ -735,13 +735,14 @@ __device__ __forceinline__ void dedup_unit(const DrawArgs &A, const vr_shader_pa
 // grid-stride over every unit from base on (stride = the grid).  Grid-stride
 // serves the units of a dynamic draw beyond the fewest it can have within
 // the same launch; it is used without prefix outputs only, since the
-// look-back needs each unit's predecessor running or done.  The hashing
-// modes are held to eight wavefronts per SIMD (64 VGPRs, 78 SGPRs; their
-// LDS allows it): the extra wavefront hides more of a unit's serial
-// latency.  The sort stays at its natural allocation: its LDS caps it at
-// six workgroups per CU, and the bound would only add spills.
-template <int NT, int MODE, int KIND>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MODE == kSort ? 7 : 8))) void k_dedup(DrawArgs A, vr_shader_params sh, uint32_t base, uint32_t stride) {
+// look-back needs each unit's predecessor running or done.  With OCC the
+// kernel is held to eight wavefronts per SIMD (seven for the sort, whose
+// registers would otherwise spill): the host picks it only when the unit's
+// LDS lets that many workgroups reside, and then the extra wavefronts hide
+// more of a unit's serial latency; otherwise the bound would only add
+// spills.
+template <int NT, int MODE, int KIND, bool OCC>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC ? (MODE == kSort ? 7 : 8) : 1))) void k_dedup(DrawArgs A, vr_shader_params sh, uint32_t base, uint32_t stride) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     if (base == 0) clear_counters(A);
     const uint32_t nb = launch_units(A, batch_count(A));

@@ -256,27 +256,44 @@ vr_status check_args(vr_ctx *c, uint64_t num_indices, uint32_t num_vertices, con
 // fewest; without prefix outputs (units in any order) the same workgroups
 // take the rest grid-stride, else a second launch has one workgroup per
 // possible further unit.
-template <int NT, int MODE, int KIND>
+template <int NT, int MODE, int KIND, bool OCC>
 void launch_dedup(vr_ctx *c, const DrawArgs &A, const vr_shader_params &sh, uint32_t lds, uint64_t units) {
     uint64_t first = units;
     if (A.plan) first = std::min<uint64_t>(units, (A.T + A.batch_tris - 1) / A.batch_tris);
     const bool stride = A.plan && !A.need_prefix && first > 0 && units > first;
     if (first)
-        hipLaunchKernelGGL((k_dedup<NT, MODE, KIND>), dim3((uint32_t)first), dim3(NT), lds, c->stream, A, sh, 0u,
-                           stride ? (uint32_t)first : 0u);
+        hipLaunchKernelGGL((k_dedup<NT, MODE, KIND, OCC>), dim3((uint32_t)first), dim3(NT), lds, c->stream, A, sh,
+                           0u, stride ? (uint32_t)first : 0u);
     if (units > first && !stride)
-        hipLaunchKernelGGL((k_dedup<NT, MODE, KIND>), dim3((uint32_t)(units - first)), dim3(NT), lds, c->stream, A,
-                           sh, (uint32_t)first, 0u);
+        hipLaunchKernelGGL((k_dedup<NT, MODE, KIND, OCC>), dim3((uint32_t)(units - first)), dim3(NT), lds,
+                           c->stream, A, sh, (uint32_t)first, 0u);
+}
+
+// Whether a dedup launch of nt threads and lds bytes per workgroup takes the
+// occupancy-bound kernel: only for 128 and 256 threads, and only when the
+// LDS lets eight wavefronts per SIMD reside (seven for the sort).
+bool dedup_occupancy_bound(const vr_ctx *c, int mode, uint32_t nt, uint32_t lds) {
+    if (nt != 128 && nt != 256) return false;
+    const uint32_t target = mode == kSort ? 7u : 8u;          // wavefronts per SIMD
+    const uint32_t groups = target * 4u / (nt / kWave);        // workgroups per CU for them
+    return (uint64_t)groups * (lds + 64u) <= c->lds_limit;     // + the kernel's static LDS
 }
 
 template <int MODE, int KIND>
 void dispatch_nt(vr_ctx *c, uint32_t nt, const DrawArgs &A, const vr_shader_params &sh, uint32_t lds, uint64_t units) {
+    const bool occ = dedup_occupancy_bound(c, MODE, nt, lds);
     switch (nt) {
-    case 64: launch_dedup<64, MODE, KIND>(c, A, sh, lds, units); break;
-    case 128: launch_dedup<128, MODE, KIND>(c, A, sh, lds, units); break;
-    case 256: launch_dedup<256, MODE, KIND>(c, A, sh, lds, units); break;
-    case 512: launch_dedup<512, MODE, KIND>(c, A, sh, lds, units); break;
-    default: launch_dedup<1024, MODE, KIND>(c, A, sh, lds, units); break;
+    case 64: launch_dedup<64, MODE, KIND, false>(c, A, sh, lds, units); break;
+    case 128:
+        if (occ) launch_dedup<128, MODE, KIND, true>(c, A, sh, lds, units);
+        else launch_dedup<128, MODE, KIND, false>(c, A, sh, lds, units);
+        break;
+    case 256:
+        if (occ) launch_dedup<256, MODE, KIND, true>(c, A, sh, lds, units);
+        else launch_dedup<256, MODE, KIND, false>(c, A, sh, lds, units);
+        break;
+    case 512: launch_dedup<512, MODE, KIND, false>(c, A, sh, lds, units); break;
+    default: launch_dedup<1024, MODE, KIND, false>(c, A, sh, lds, units); break;
     }
 }
 
@@ -493,30 +510,46 @@ struct FrameLaunch {
     unsigned long long *total_inv;
 };
 
-template <int MODE, int KIND>
+template <int MODE, int KIND, bool OCC>
 void launch_frame_variant(const FrameLaunch &L, const FrameVariant &v, hipStream_t s) {
-    hipLaunchKernelGGL((k_frame<MODE, KIND>), dim3(v.grid), dim3(kFrameNT), v.lds_total, s, L.draws, L.order, v.lo,
-                       v.hi, L.shaders, (const uint32_t *)L.unit_base, (const uint32_t *)L.slot_base, L.agg,
+    hipLaunchKernelGGL((k_frame<MODE, KIND, OCC>), dim3(v.grid), dim3(kFrameNT), v.lds_total, s, L.draws, L.order,
+                       v.lo, v.hi, L.shaders, (const uint32_t *)L.unit_base, (const uint32_t *)L.slot_base, L.agg,
                        v.unit_lds, v.ballot_stride, L.err, L.total_inv);
 }
 
-template <int MODE, int KIND>
+template <int MODE, int KIND, bool OCC>
 int frame_variant_occupancy(uint32_t lds) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_frame<MODE, KIND>, kFrameNT, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_frame<MODE, KIND, OCC>, kFrameNT, lds) !=
+            hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     return per_cu;
 }
 
+template <int MODE, int KIND, bool OCC>
+int frame_variant_kind(const FrameLaunch *L, const FrameVariant &v, hipStream_t s, bool launch) {
+    return launch ? (launch_frame_variant<MODE, KIND, OCC>(*L, v, s), 0)
+                  : frame_variant_occupancy<MODE, KIND, OCC>(v.lds_total);
+}
+
 // Resident workgroups per CU of a variant's kernel (launch = false), or its
-// launch (launch = true); mode and kind select the instantiation.
+// launch (launch = true); mode, kind and the occupancy bound (hashing modes
+// only) select the instantiation.
 template <int MODE>
 int frame_variant_mode(const FrameLaunch *L, const FrameVariant &v, hipStream_t s, bool launch) {
+    constexpr bool kHashing = MODE == kFrameHash || MODE == kFramePHash;
+    if (kHashing && v.occ) {
+        switch (v.kind) {
+        case 0: return frame_variant_kind<MODE, 0, kHashing>(L, v, s, launch);
+        case 1: return frame_variant_kind<MODE, 1, kHashing>(L, v, s, launch);
+        default: return frame_variant_kind<MODE, 2, kHashing>(L, v, s, launch);
+        }
+    }
     switch (v.kind) {
-    case 0: return launch ? (launch_frame_variant<MODE, 0>(*L, v, s), 0) : frame_variant_occupancy<MODE, 0>(v.lds_total);
-    case 1: return launch ? (launch_frame_variant<MODE, 1>(*L, v, s), 0) : frame_variant_occupancy<MODE, 1>(v.lds_total);
-    default: return launch ? (launch_frame_variant<MODE, 2>(*L, v, s), 0) : frame_variant_occupancy<MODE, 2>(v.lds_total);
+    case 0: return frame_variant_kind<MODE, 0, false>(L, v, s, launch);
+    case 1: return frame_variant_kind<MODE, 1, false>(L, v, s, launch);
+    default: return frame_variant_kind<MODE, 2, false>(L, v, s, launch);
     }
 }
 
@@ -671,6 +704,9 @@ vr_status frame_variants(vr_ctx *c, const DrawDesc *desc, const FrameNeeds *need
         if (v.lds_total > c->lds_limit)
             return fail(c, VR_ERR_ARG, "frame variant needs %u B of LDS per workgroup (limit %zu)", v.lds_total,
                         c->lds_limit);
+        // hashing variants take the occupancy-bound kernel when eight
+        // workgroups (eight wavefronts per SIMD) fit in the LDS
+        v.occ = (v.mode == kFrameHash || v.mode == kFramePHash) && 8ull * (v.lds_total + 64u) <= c->lds_limit;
         const uint64_t ck = ((uint64_t)(v.mode * 3 + v.kind) << 32) | v.lds_total;
         int per_cu;
         auto it = occ_cache ? occ_cache->find(ck) : std::map<uint64_t, int>::iterator();
