@@ -763,6 +763,8 @@ def main():
     ap.add_argument("--only", default=None, help="run only this strategy in each step (profiling)")
     ap.add_argument("--no-scene", action="store_true", help="skip the many-draw frame measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--serve-requests", type=int, default=2000, metavar="N",
+                    help="requests of the serving stream (30000 is the full 60 s at 500 requests/s)")
     ap.add_argument("--autotune-table", default=None, metavar="JSON",
                     help="scene: read the autotuner's choices from this file if it exists, else write them")
     ap.add_argument("--no-extra", action="store_true",
@@ -980,7 +982,7 @@ def main():
     serving = None
     if not args.no_serve and not args.only:
         try:
-            serving = serving_benchmark(stage)
+            serving = serving_benchmark(stage, n=args.serve_requests)
         except Exception as exc:
             serving = {"error": repr(exc)}
 
