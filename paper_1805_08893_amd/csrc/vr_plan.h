@@ -451,9 +451,12 @@ __global__ __launch_bounds__(256) void k_plan_table(PlanArgs P, uint16_t *tab) {
 }
 
 // Composes tables [g*fan, min(count, g*fan + fan)) of `in` into table g of
-// `out` (fan = plan_fan_in(tmax)).
+// `out` (fan = plan_fan_in(tmax)).  On the way it records, for every entry j
+// of the group, the entry of each member table (`pre`, laid out as `in`):
+// once the group's entry is known, a member's entry is one lookup.
 __global__ __launch_bounds__(512) void k_plan_compose(uint32_t tmax, uint32_t count, const uint16_t *in,
-                                                      uint16_t *out, const uint32_t *fail, uint32_t epoch) {
+                                                      uint16_t *out, uint16_t *pre, const uint32_t *fail,
+                                                      uint32_t epoch) {
     extern __shared__ uint16_t s_t[];   // fan * tmax
     if (plan_is_aligned(fail, epoch)) return;
     const uint32_t fan = plan_fan_in(tmax);
@@ -464,7 +467,10 @@ __global__ __launch_bounds__(512) void k_plan_compose(uint32_t tmax, uint32_t co
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < tmax; j += 512) {
         uint32_t x = j;
-        for (uint32_t k = 0; k < k1 - k0 && x != kEnd; ++k) x = s_t[k * tmax + x];
+        for (uint32_t k = 0; k < k1 - k0; ++k) {
+            pre[(size_t)(k0 + k) * tmax + j] = (uint16_t)x;
+            if (x != kEnd) x = s_t[k * tmax + x];
+        }
         out[(size_t)g * tmax + j] = (uint16_t)x;
     }
 }
@@ -487,32 +493,23 @@ __global__ __launch_bounds__(256) void k_plan_top(uint32_t tmax, uint32_t count,
     }
 }
 
-// Pushes entries one level down: group g of `tab` (fan tables) receives its
-// entry from up_entry[g] and records its members' entries.
-__global__ __launch_bounds__(256) void k_plan_resolve(uint32_t tmax, uint32_t count, const uint16_t *tab,
+// Pushes entries one level down: table i of a level (of `count`) gets its
+// entry from its group's entry up_entry[i / fan] through the member entries
+// `pre` recorded by k_plan_compose.  One thread per table.
+__global__ __launch_bounds__(256) void k_plan_resolve(uint32_t tmax, uint32_t count, const uint16_t *pre,
                                                       const uint16_t *up_entry, uint16_t *entry,
                                                       const uint32_t *fail, uint32_t epoch) {
-    extern __shared__ uint16_t s_t[];
     if (plan_is_aligned(fail, epoch)) return;
-    const uint32_t fan = plan_fan_in(tmax);
-    const uint32_t g = blockIdx.x;
-    const uint32_t k0 = g * fan, k1 = min(count, k0 + fan);
-    const uint32_t m = (k1 - k0) * tmax;
-    for (uint32_t i = threadIdx.x; i < m; i += 256) s_t[i] = tab[(size_t)k0 * tmax + i];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t x = up_entry[g];
-        for (uint32_t k = 0; k < k1 - k0; ++k) {
-            entry[k0 + k] = (uint16_t)x;
-            if (x != kEnd) x = s_t[k * tmax + x];
-        }
-    }
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const uint32_t x = up_entry[i / plan_fan_in(tmax)];
+    entry[i] = x == kEnd ? kEnd : pre[(size_t)i * tmax + x];
 }
 
 // Level 0, merged with listing and packing.  Segment s receives its entry:
-// directly from `up` when the tables have one level, else its group's entry
-// at level 1 pushed through the tables of the group's earlier segments
-// (staged in LDS).  One thread follows next() from the entry (next() of the
+// directly from `up` when the tables have one level, else from its group's
+// entry at level 1 through the member entries k_plan_compose recorded
+// (`pre`).  One thread follows next() from the entry (next() of the
 // segment staged in LDS) and lists the segment's batch starts; the segment
 // publishes its count and resolves its offset in the plan with a decoupled
 // look-back over the segments, then the block copies its starts there.  The
@@ -552,24 +549,20 @@ __device__ __forceinline__ uint32_t plan_lookback(unsigned long long *status, ui
     return excl;
 }
 
-__global__ __launch_bounds__(256) void k_plan_emit(PlanArgs P, const uint16_t *tab0, const uint16_t *up,
+__global__ __launch_bounds__(256) void k_plan_emit(PlanArgs P, const uint16_t *pre0, const uint16_t *up,
                                                    uint32_t direct, unsigned long long *status, uint32_t *plan) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ uint32_t s_cnt, s_off;
     if (plan_is_aligned(P.fail, P.epoch)) return;
     const uint32_t tid = threadIdx.x, s = blockIdx.x;
     const uint32_t b = seg_lo(P, s), e = seg_hi(P, s), len = e - b;
-    const uint32_t fan = plan_fan_in(P.tmax), k0 = s / fan * fan;
     uint32_t *s_nx = (uint32_t *)smem;                    // seg_len entries
     uint32_t *s_cut = s_nx + P.seg_len;                   // seg_len entries
-    uint16_t *s_t = (uint16_t *)(s_cut + P.seg_len);      // the group's earlier tables
     for (uint32_t i = tid; i < len; i += 256) s_nx[i] = P.next[b + i];
-    const uint32_t m = direct ? 0u : (s - k0) * P.tmax;
-    for (uint32_t i = tid; i < m; i += 256) s_t[i] = tab0[(size_t)k0 * P.tmax + i];
     __syncthreads();
     if (tid == 0) {
-        uint32_t x = direct ? up[s] : up[s / fan];
-        for (uint32_t k = 0; k < m / max(P.tmax, 1u) && x != kEnd; ++k) x = s_t[k * P.tmax + x];
+        uint32_t x = direct ? up[s] : up[s / plan_fan_in(P.tmax)];
+        if (!direct && x != kEnd) x = pre0[(size_t)s * P.tmax + x];
         uint32_t n = 0;
         if (x != kEnd)
             for (uint32_t t = b + x; t < e; t = s_nx[t - b]) s_cut[n++] = t;

@@ -416,12 +416,15 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     while (counts.back() > fan) counts.push_back((counts.back() + fan - 1) / fan);
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t bytes = al(4ull * T);
-    std::vector<size_t> tab_off, ent_off;
-    for (uint32_t cnt : counts) {
+    std::vector<size_t> tab_off, ent_off, pre_off;
+    for (size_t l = 0; l < counts.size(); ++l) {
+        const uint32_t cnt = counts[l];
         tab_off.push_back(bytes);
         bytes += al(2ull * cnt * tmax);
         ent_off.push_back(bytes);
         bytes += al(2ull * cnt);
+        pre_off.push_back(bytes);   // member entries, for the levels that are composed
+        if (l + 1 < counts.size()) bytes += al(2ull * cnt * tmax);
     }
     vr_status st = ensure(c, c->plan_work, bytes);
     if (st != VR_OK) return st;
@@ -433,6 +436,7 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     uint32_t *next = (uint32_t *)base;
     auto tab = [&](size_t l) { return (uint16_t *)(base + tab_off[l]); };
     auto ent = [&](size_t l) { return (uint16_t *)(base + ent_off[l]); };
+    auto pre = [&](size_t l) { return (uint16_t *)(base + pre_off[l]); };
     PlanArgs P{};
     P.idx = d_idx;
     P.V = V;
@@ -459,18 +463,18 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
     const uint32_t grp_lds = 2 * fan * tmax;
     for (size_t l = 0; l + 1 < counts.size(); ++l)
         hipLaunchKernelGGL(k_plan_compose, dim3(counts[l + 1]), dim3(512), grp_lds, c->stream, tmax, counts[l],
-                           (const uint16_t *)tab(l), tab(l + 1), (const uint32_t *)P.fail, P.epoch);
+                           (const uint16_t *)tab(l), tab(l + 1), pre(l), (const uint32_t *)P.fail, P.epoch);
     const size_t top = counts.size() - 1;
     hipLaunchKernelGGL(k_plan_top, dim3(1), dim3(256), 2 * counts[top] * tmax, c->stream, tmax, counts[top],
                        (const uint16_t *)tab(top), ent(top), (const uint32_t *)P.fail, P.epoch);
     for (size_t l = top; l-- > 1;)
-        hipLaunchKernelGGL(k_plan_resolve, dim3(counts[l + 1]), dim3(256), grp_lds, c->stream, tmax, counts[l],
-                           (const uint16_t *)tab(l), (const uint16_t *)ent(l + 1), ent(l), (const uint32_t *)P.fail,
+        hipLaunchKernelGGL(k_plan_resolve, dim3((counts[l] + 255) / 256), dim3(256), 0, c->stream, tmax, counts[l],
+                           (const uint16_t *)pre(l), (const uint16_t *)ent(l + 1), ent(l), (const uint32_t *)P.fail,
                            P.epoch);
     // level 0: entries, batch starts and packing in one launch
     const uint32_t direct = top == 0 ? 1u : 0u;
-    hipLaunchKernelGGL(k_plan_emit, dim3(nseg), dim3(256), 8 * L + (direct ? 0u : grp_lds), c->stream, P,
-                       (const uint16_t *)tab(0), (const uint16_t *)ent(direct ? 0 : 1), direct,
+    hipLaunchKernelGGL(k_plan_emit, dim3(nseg), dim3(256), 8 * L, c->stream, P,
+                       (const uint16_t *)(direct ? nullptr : pre(0)), (const uint16_t *)ent(direct ? 0 : 1), direct,
                        (unsigned long long *)c->plan_status.ptr, d_plan);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
