@@ -17,6 +17,7 @@ oracle timed on a bounded sample.
 import argparse
 import glob
 import hashlib
+import re
 import json
 import os
 import sys
@@ -61,15 +62,20 @@ def host_cpu_model():
 
 
 def kernel_source_sha():
-    """Hash of the kernel sources: HBM-traffic counters are used only when they
-    were taken on exactly these sources."""
+    """Hash of the kernel sources with comments and blank lines removed:
+    HBM-traffic counters are used only when they were taken on exactly this
+    code (a comment edit does not make them stale)."""
     h = hashlib.sha256()
     files = sorted(glob.glob(os.path.join(ROOT, "paper_1805_08893_amd", "csrc", "*"))) + \
         [os.path.join(ROOT, "include", "vr.h")]
     for f in files:
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode())
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(os.path.basename(f).encode())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

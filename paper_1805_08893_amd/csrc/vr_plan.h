@@ -9,25 +9,29 @@
 //
 //  1. next(c) for every c (k_plan_next).  A workgroup stages the indices of
 //     a block of starts plus N_pmax triangles in LDS and finds every corner's
-//     previous and next occurrence in that window (hash slots, bucketed by a
-//     counting sort).  The distinct count of the full N_pmax window of every
-//     start follows from a difference array; where it is within N_u, next(c)
-//     is the window's end.  Each lane then sweeps a few consecutive starts
-//     with two pointers: moving the start past a triangle drops its corners
-//     that were new and makes new the next occurrences of its corners inside
-//     the batch; the end then advances while the budget holds.
+//     previous occurrence in that window (hash slots, bucketed by a counting
+//     sort).  The distinct count of the full N_pmax window of every start
+//     follows from a difference array; where it is within N_u, next(c) is
+//     the window's end.  Otherwise the start's lane finds the cut: a corner
+//     is new to the batch [c, e) exactly when its previous occurrence lies
+//     before c, so the count of a shorter batch is the window's count minus
+//     the new corners of the triangles dropped from its end; the lane drops
+//     triangles from the end while the count is over N_u (or, when the
+//     window is more than twice over, adds them from c until it would be).
 //  2. Transfer tables (k_plan_table, k_plan_compose).  The triangles are cut
 //     into segments of L >= N_pmax triangles.  The chain's state at a
 //     segment boundary is its first position at or after the boundary, which
 //     lies within N_pmax triangles of it.  For every possible entry offset a
 //     table gives the exit offset at the segment's end (one lane per entry
 //     follows next() in LDS); tables of consecutive ranges are composed into
-//     one, level by level, until few remain.
+//     one, level by level, until few remain, and each composition records
+//     every member table's entry for every entry of its group.
 //  3. Resolution (k_plan_top, k_plan_resolve, k_plan_emit).  The top tables
 //     are applied in order from entry 0 and entries are pushed down the
-//     levels; at level 0 every segment takes its entry, walks next() from it
-//     to list its batch starts, and copies them into [B, start_0, ..,
-//     start_{B-1}, T] at an offset found by a decoupled look-back.
+//     levels through those records; at level 0 every segment takes its
+//     entry, walks next() from it to list its batch starts, and copies them
+//     into [B, start_0, .., start_{B-1}, T] at an offset found by a
+//     decoupled look-back.
 // Every step does bounded parallel work whatever the batch structure; the
 // result equals the sequential chain exactly.
 #pragma once
