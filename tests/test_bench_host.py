@@ -37,6 +37,25 @@ def test_kernel_source_hash_is_stable():
     assert a == b and len(a) == 16
 
 
+def _sources_hash(tmp_path, kernel, header, monkeypatch):
+    (tmp_path / "paper_1805_08893_amd" / "csrc").mkdir(parents=True, exist_ok=True)
+    (tmp_path / "include").mkdir(exist_ok=True)
+    (tmp_path / "paper_1805_08893_amd" / "csrc" / "k.h").write_text(kernel)
+    (tmp_path / "include" / "vr.h").write_text(header)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    return bench.kernel_source_sha()
+
+
+def test_kernel_source_hash_ignores_comments_but_not_code(tmp_path, monkeypatch):
+    """Counters stay valid across comment edits and become stale on any code edit."""
+    code = "int f(int x) {\n    return x + 1;\n}\n"
+    base = _sources_hash(tmp_path, code, "int g(void);\n", monkeypatch)
+    commented = "// adds one\n/* a block\n   comment */\nint f(int x) {   // trailing\n\n    return x + 1;\n}\n"
+    assert _sources_hash(tmp_path, commented, "/* api */\nint g(void);\n", monkeypatch) == base
+    assert _sources_hash(tmp_path, code.replace("+ 1", "+ 2"), "int g(void);\n", monkeypatch) != base
+    assert _sources_hash(tmp_path, code, "int g(int);\n", monkeypatch) != base
+
+
 def test_host_cpu_model_is_text_or_none():
     m = bench.host_cpu_model()
     assert m is None or (isinstance(m, str) and m)
