@@ -33,9 +33,10 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 METRIC = "triangles/s & shading rate per strategy vs no-reuse; p50/p99 draw latency"
 
-# main kernel of each draw in the step (Phong shading instantiation)
-KERNEL_NAMES = {"naive": "k_naive<1>", "static_ballot": "k_ballot<1>", "dyn_sort": "k_dedup<256, 0, 1>",
-                "dyn_hash": "k_dedup<256, 1, 1>", "dyn_phash": "k_dedup<256, 2, 1>"}
+# main kernel of each draw in the step (Phong shading instantiation; the
+# step's dedup units fit the LDS of the occupancy-bound kernels, which they take)
+KERNEL_NAMES = {"naive": "k_naive<1>", "static_ballot": "k_ballot<1>", "dyn_sort": "k_dedup<256, 0, 1, true>",
+                "dyn_hash": "k_dedup<256, 1, 1, true>", "dyn_phash": "k_dedup<256, 2, 1, true>"}
 
 
 def shader_flops(sp):
