@@ -437,11 +437,15 @@ __global__ __launch_bounds__(NextClass<TMC>::threads) void k_plan_next(PlanArgs 
 // lane per entry follows next() through the segment (staged in LDS).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_plan_table(PlanArgs P, uint16_t *tab) {
-    extern __shared__ uint32_t s_nx[];   // seg_len entries
+    extern __shared__ __attribute__((aligned(16))) uint32_t s_nx[];   // seg_len entries
     if (plan_is_aligned(P.fail, P.epoch)) return;
     const uint32_t s = blockIdx.x;
     const uint32_t b = seg_lo(P, s), e = seg_hi(P, s), len = e - b;
-    for (uint32_t i = threadIdx.x; i < len; i += 256) s_nx[i] = P.next[b + i];
+    {   // 16-byte loads: a segment starts at a multiple of 2048 entries
+        const uint4 *src = (const uint4 *)(P.next + b);
+        for (uint32_t i = threadIdx.x; i < len / 4; i += 256) ((uint4 *)s_nx)[i] = src[i];
+        for (uint32_t i = len / 4 * 4 + threadIdx.x; i < len; i += 256) s_nx[i] = P.next[b + i];
+    }
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < P.tmax; j += 256) {
         uint16_t out = kEnd;
@@ -510,10 +514,14 @@ __global__ __launch_bounds__(256) void k_plan_resolve(uint32_t tmax, uint32_t co
     entry[i] = x == kEnd ? kEnd : pre[(size_t)i * tmax + x];
 }
 
-// Level 0, merged with listing and packing.  Segment s receives its entry:
-// directly from `up` when the tables have one level, else from its group's
-// entry at level 1 through the member entries k_plan_compose recorded
-// (`pre`).  One thread follows next() from the entry (next() of the
+// Level 0, merged with listing and packing.  Segment s receives its entry
+// (`mode`): 0, directly from `up` (the tables have one level); 1, from its
+// group's entry at level 1 (`up`, pushed down by k_plan_top and
+// k_plan_resolve) through the member entries k_plan_compose recorded
+// (`pre0`); 2, with exactly two levels, from its group's entry found by the
+// block itself, walking the level-1 tables before its group (`up`, staged in
+// LDS) from entry 0, then through `pre0` (no k_plan_top launch).  One thread
+// follows next() from the entry (next() of the
 // segment staged in LDS) and lists the segment's batch starts; the segment
 // publishes its count and resolves its offset in the plan with a decoupled
 // look-back over the segments, then the block copies its starts there.  The
@@ -554,7 +562,7 @@ __device__ __forceinline__ uint32_t plan_lookback(unsigned long long *status, ui
 }
 
 __global__ __launch_bounds__(256) void k_plan_emit(PlanArgs P, const uint16_t *pre0, const uint16_t *up,
-                                                   uint32_t direct, unsigned long long *status, uint32_t *plan) {
+                                                   uint32_t mode, unsigned long long *status, uint32_t *plan) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ uint32_t s_cnt, s_off;
     if (plan_is_aligned(P.fail, P.epoch)) return;
@@ -562,11 +570,30 @@ __global__ __launch_bounds__(256) void k_plan_emit(PlanArgs P, const uint16_t *p
     const uint32_t b = seg_lo(P, s), e = seg_hi(P, s), len = e - b;
     uint32_t *s_nx = (uint32_t *)smem;                    // seg_len entries
     uint32_t *s_cut = s_nx + P.seg_len;                   // seg_len entries
-    for (uint32_t i = tid; i < len; i += 256) s_nx[i] = P.next[b + i];
+    uint16_t *s_t = (uint16_t *)(s_cut + P.seg_len);      // mode 2: level-1 tables before the group
+    const uint32_t g = s / plan_fan_in(P.tmax);
+    // 16-byte loads: next() of a segment starts at a multiple of 2048 entries
+    // and the level-1 tables at a 256-byte boundary of the planner's scratch
+    {
+        const uint4 *src = (const uint4 *)(P.next + b);
+        for (uint32_t i = tid; i < len / 4; i += 256) ((uint4 *)s_nx)[i] = src[i];
+        for (uint32_t i = len / 4 * 4 + tid; i < len; i += 256) s_nx[i] = P.next[b + i];
+    }
+    const uint32_t m = mode == 2 ? g * P.tmax : 0u;
+    for (uint32_t i = tid; i < m / 8; i += 256) ((uint4 *)s_t)[i] = ((const uint4 *)up)[i];
+    for (uint32_t i = m / 8 * 8 + tid; i < m; i += 256) s_t[i] = up[i];
     __syncthreads();
     if (tid == 0) {
-        uint32_t x = direct ? up[s] : up[s / plan_fan_in(P.tmax)];
-        if (!direct && x != kEnd) x = pre0[(size_t)s * P.tmax + x];
+        uint32_t x;
+        if (mode == 0) {
+            x = up[s];
+        } else if (mode == 1) {
+            x = up[g];
+        } else {
+            x = 0;
+            for (uint32_t k = 0; k < g && x != kEnd; ++k) x = s_t[k * P.tmax + x];
+        }
+        if (mode != 0 && x != kEnd) x = pre0[(size_t)s * P.tmax + x];
         uint32_t n = 0;
         if (x != kEnd)
             for (uint32_t t = b + x; t < e; t = s_nx[t - b]) s_cut[n++] = t;

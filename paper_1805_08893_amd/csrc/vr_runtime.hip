@@ -465,16 +465,21 @@ vr_status build_plan(vr_ctx *c, const uint32_t *d_idx, uint32_t T, uint32_t V, u
         hipLaunchKernelGGL(k_plan_compose, dim3(counts[l + 1]), dim3(512), grp_lds, c->stream, tmax, counts[l],
                            (const uint16_t *)tab(l), tab(l + 1), pre(l), (const uint32_t *)P.fail, P.epoch);
     const size_t top = counts.size() - 1;
-    hipLaunchKernelGGL(k_plan_top, dim3(1), dim3(256), 2 * counts[top] * tmax, c->stream, tmax, counts[top],
-                       (const uint16_t *)tab(top), ent(top), (const uint32_t *)P.fail, P.epoch);
+    // with two levels every emit block walks the (at most fan) level-1
+    // tables before its group itself, so the top kernel is not launched
+    const uint32_t emit_mode = top == 0 ? 0u : (top == 1 ? 2u : 1u);
+    if (emit_mode != 2)
+        hipLaunchKernelGGL(k_plan_top, dim3(1), dim3(256), 2 * counts[top] * tmax, c->stream, tmax, counts[top],
+                           (const uint16_t *)tab(top), ent(top), (const uint32_t *)P.fail, P.epoch);
     for (size_t l = top; l-- > 1;)
         hipLaunchKernelGGL(k_plan_resolve, dim3((counts[l] + 255) / 256), dim3(256), 0, c->stream, tmax, counts[l],
                            (const uint16_t *)pre(l), (const uint16_t *)ent(l + 1), ent(l), (const uint32_t *)P.fail,
                            P.epoch);
     // level 0: entries, batch starts and packing in one launch
-    const uint32_t direct = top == 0 ? 1u : 0u;
-    hipLaunchKernelGGL(k_plan_emit, dim3(nseg), dim3(256), 8 * L, c->stream, P,
-                       (const uint16_t *)(direct ? nullptr : pre(0)), (const uint16_t *)ent(direct ? 0 : 1), direct,
+    const uint16_t *up = emit_mode == 0 ? ent(0) : (emit_mode == 1 ? ent(1) : tab(1));
+    const uint32_t emit_lds = 8 * L + (emit_mode == 2 ? 2 * counts[1] * tmax : 0u);
+    hipLaunchKernelGGL(k_plan_emit, dim3(nseg), dim3(256), emit_lds, c->stream, P,
+                       (const uint16_t *)(emit_mode == 0 ? nullptr : pre(0)), up, emit_mode,
                        (unsigned long long *)c->plan_status.ptr, d_plan);
     VR_HIP(c, hipGetLastError());
     return VR_OK;
