@@ -17,7 +17,6 @@ oracle timed on a bounded sample.
 import argparse
 import glob
 import hashlib
-import re
 import json
 import os
 import sys
@@ -62,6 +61,31 @@ def host_cpu_model():
     return None
 
 
+def strip_c_comments(text):
+    """C/C++ source without its // and /* */ comments; string and character
+    literals (which may hold those markers) are kept as they are."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":                       # a literal, up to its unescaped closing quote
+            j = i + 1
+            while j < n and text[j] != c and text[j] != "\n":
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            while i < n and text[i] != "\n":
+                i += 1
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return "".join(out)
+
+
 def kernel_source_sha():
     """Hash of the kernel sources with comments and blank lines removed:
     HBM-traffic counters are used only when they were taken on exactly this
@@ -71,9 +95,7 @@ def kernel_source_sha():
         [os.path.join(ROOT, "include", "vr.h")]
     for f in files:
         with open(f, encoding="utf-8") as fh:
-            text = fh.read()
-        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        text = re.sub(r"//[^\n]*", "", text)
+            text = strip_c_comments(fh.read())
         code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
         h.update(os.path.basename(f).encode())
         h.update(code.encode())

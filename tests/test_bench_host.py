@@ -56,6 +56,13 @@ def test_kernel_source_hash_ignores_comments_but_not_code(tmp_path, monkeypatch)
     assert _sources_hash(tmp_path, code, "int g(int);\n", monkeypatch) != base
 
 
+def test_comment_stripping_keeps_literals():
+    src = 'const char *u = "http://x/*y*/"; // note\nchar c = \'/\'; /* a\n b */ int k = 1; // "q"\n'
+    out = bench.strip_c_comments(src)
+    assert '"http://x/*y*/"' in out and "'/'" in out and "int k = 1;" in out
+    assert "note" not in out and "a\n b" not in out and '"q"' not in out
+
+
 def test_host_cpu_model_is_text_or_none():
     m = bench.host_cpu_model()
     assert m is None or (isinstance(m, str) and m)
